@@ -1,0 +1,157 @@
+"""ctypes wrapper for the FP64 CPU oracle (``lagp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
+benchmark's CPU-baseline leg are the only users.  The product path never
+imports this package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lagp_oracle.c")
+LIB = os.path.join(HERE, "liblagp_oracle.so")
+
+OK, NOTPD, EINVAL, ENOMEM = 0, 1, -1, -2
+
+_lib = None
+
+
+def compile_source(src: str, out: str) -> str:
+    """Compile one oracle source file with gcc (FP64, no FMA contraction, OpenMP)."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB):
+        compile_source(SRC, LIB)
+    return LIB
+
+
+def load(path: str):
+    """Load an oracle build from ``path`` with argument types configured."""
+    L = C.CDLL(path)
+    _configure(L)
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = load(LIB)
+    return _lib
+
+
+def _configure(L):
+    P = C.c_void_p
+    i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+    L.lagp_oracle_knn.argtypes = [P, i64, i32, P, i64, P, P]
+    L.lagp_oracle_predict.argtypes = [P, P, i32, P, P, i32, f64, f64, P]
+    L.lagp_oracle_alc.argtypes = [P, i32, P, P, i32, P, i64, f64, f64, P, P, P, P]
+    L.lagp_oracle_alc_brute.argtypes = [P, i32, P, P, i32, P, i64, f64, f64, P]
+    L.lagp_oracle_local.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, P, P]
+    L.lagp_oracle_batch.argtypes = [P, P, i64, i32, P, i64, i32, i32, i64, P, P, f64, f64,
+                                    P, i64, P, P, i32]
+    for f in (L.lagp_oracle_knn, L.lagp_oracle_predict, L.lagp_oracle_alc,
+              L.lagp_oracle_alc_brute, L.lagp_oracle_local, L.lagp_oracle_batch,
+              L.lagp_oracle_max_threads):
+        f.restype = C.c_int
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def knn(X, x, M, L=None):
+    """Indices and squared distances of the M nearest design points of x."""
+    X = _f64(X); x = _f64(x)
+    idx = np.empty(M, np.int32); d2 = np.empty(M, np.float64)
+    rc = (L or lib()).lagp_oracle_knn(_ptr(X), X.shape[0], X.shape[1], _ptr(x), M, _ptr(idx), _ptr(d2))
+    if rc != OK:
+        raise ValueError(f"oracle knn failed: {rc}")
+    return idx, d2
+
+
+def predict(X, y, x, D, d, g, L=None):
+    """{mean, s2, var, v_n(x), psi} from the design indices D (fresh Cholesky)."""
+    X = _f64(X); y = _f64(y); x = _f64(x); D = _i32(D)
+    out = np.empty(5, np.float64)
+    rc = (L or lib()).lagp_oracle_predict(_ptr(X), _ptr(y), X.shape[1], _ptr(x), _ptr(D), len(D), d, g, _ptr(out))
+    return rc, out
+
+
+def alc(X, x, D, cand, d, g, L=None):
+    """(alc, v_j(c), cov_j(x,c), v_j(x)) for candidates ``cand`` given design D."""
+    X = _f64(X); x = _f64(x); D = _i32(D); cand = _i32(cand)
+    a = np.empty(len(cand)); v = np.empty(len(cand)); cv = np.empty(len(cand)); vx = np.empty(1)
+    rc = (L or lib()).lagp_oracle_alc(_ptr(X), X.shape[1], _ptr(x), _ptr(D), len(D), _ptr(cand), len(cand),
+                               d, g, _ptr(a), _ptr(v), _ptr(cv), _ptr(vx))
+    if rc != OK:
+        raise ValueError(f"oracle alc failed: {rc}")
+    return a, v, cv, float(vx[0])
+
+
+def alc_brute(X, x, D, cand, d, g, L=None):
+    X = _f64(X); x = _f64(x); D = _i32(D); cand = _i32(cand)
+    a = np.empty(len(cand))
+    rc = (L or lib()).lagp_oracle_alc_brute(_ptr(X), X.shape[1], _ptr(x), _ptr(D), len(D), _ptr(cand),
+                                     len(cand), d, g, _ptr(a))
+    if rc != OK:
+        raise ValueError(f"oracle brute alc failed: {rc}")
+    return a
+
+
+def local(X, y, x, n0, n, M, d, g, replay=None, L=None):
+    """Greedy ALC design + prediction at one location.
+
+    Returns (rc, sel[n], out[5] = {mean, s2, var, v_n(x), psi}, diag[n,3])."""
+    X = _f64(X); y = _f64(y); x = _f64(x)
+    sel = np.empty(n, np.int32); out = np.empty(5); diag = np.empty((n, 3))
+    rp = None if replay is None else _i32(replay)
+    rc = (L or lib()).lagp_oracle_local(_ptr(X), _ptr(y), X.shape[0], X.shape[1], _ptr(x), n0, n, M, d, g,
+                                 _ptr(rp), _ptr(sel), _ptr(out), _ptr(diag))
+    if rc < 0:
+        raise ValueError(f"oracle local failed: {rc}")
+    return rc, sel, out, diag
+
+
+def batch(X, y, XX, n0, n, M, d, g, n_per=None, M_per=None, threads=0, L=None):
+    """All locations, OpenMP over locations.
+
+    Returns (status[T], sel[T, nmax], out[T, 5])."""
+    X = _f64(X); y = _f64(y); XX = _f64(XX)
+    T = XX.shape[0]
+    npe = None if n_per is None else _i32(n_per)
+    mpe = None if M_per is None else _i32(M_per)
+    nmax = int(npe.max()) if (npe is not None and T) else n
+    sel = np.full((T, nmax), -1, np.int32)
+    out = np.empty((T, 5)); st = np.empty(T, np.int32)
+    rc = (L or lib()).lagp_oracle_batch(_ptr(X), _ptr(y), X.shape[0], X.shape[1], _ptr(XX), T, n0, n, M,
+                                 _ptr(npe), _ptr(mpe), d, g, _ptr(sel), nmax, _ptr(out), _ptr(st),
+                                 int(threads))
+    if rc < 0:
+        raise ValueError(f"oracle batch failed: {rc}")
+    return st, sel, out
+
+
+def max_threads() -> int:
+    return int(lib().lagp_oracle_max_threads())

@@ -1,0 +1,410 @@
+/*
+ * lagp_oracle.c -- FP64 CPU oracle for local approximate Gaussian-process
+ * prediction with greedy ALC local designs (Gramacy & Apley, "Local Gaussian
+ * process approximation for large computer experiments").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the benchmark's CPU-baseline leg load this library.  It shares no code,
+ * header or table with the GPU path; the product never calls it.
+ *
+ * It is deliberately plain and slow.  At every greedy step the local
+ * covariance matrix K_j is rebuilt and factorised from scratch, every
+ * candidate is solved against that factor, and the final prediction uses a
+ * fresh factorisation of K_n.  Nothing is carried from one step to the next
+ * except the list of chosen design indices.
+ *
+ * Model (Section 2): zero-mean GP, isotropic Gaussian correlation
+ *   K(a,b) = exp(-||a-b||^2 / theta)   for two distinct points,
+ * and the nugget eta is added on the diagonal of every design covariance
+ * matrix and to the self-covariance K(x,x) = 1 + eta of the predictive
+ * location and of a candidate.  Cross-covariances never carry the nugget,
+ * even where coordinates coincide (the Kronecker delta is taken on indices).
+ *
+ * Greedy local design (Section 3 with the criterion of Sections 3.2-3.3):
+ * start from the n0 nearest neighbours of x, then for j = n0..n-1 add the
+ * candidate with the largest reduction in predictive variance at x,
+ *   ALC_j(c) = v_j(x) - v_{j+1}(x | c) = cov_j(x,c)^2 / v_j(c)
+ * (eq dxy, and its partial-correlation form eq dxy2 of SM Section 4), where
+ *   v_j(c)     = 1 + eta - k_j(c)' K_j^{-1} k_j(c),
+ *   cov_j(x,c) = K(x,c)  - k_j(x)' K_j^{-1} k_j(c).
+ * Candidates are the N' nearest design points of x (Section 6).
+ *
+ * Prediction (eqs predgp and preds2 with N -> n): mean k'K^{-1}Y, scale
+ * s2 = psi * v_n(x) / n with psi = Y'K^{-1}Y, df = n, variance
+ * V = s2 * n / (n-2) = psi * v_n(x) / (n-2).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ * distances are summed over coordinates left to right with no fused
+ * multiply-add; nearest neighbours are ordered by (squared distance, index);
+ * argmax ties go to the smaller design index; a candidate whose v_j(c) is
+ * not positive scores -infinity; a failed factorisation flags the location.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_NOTPD 1
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+/* ||a-b||^2, coordinates summed left to right. */
+static double sqdist(const double *a, const double *b, int p)
+{
+    double s = 0.0;
+    for (int k = 0; k < p; k++) {
+        double t = a[k] - b[k];
+        s += t * t;
+    }
+    return s;
+}
+
+/* Isotropic Gaussian correlation of two distinct points (Section 2). */
+static double corr(const double *a, const double *b, int p, double theta)
+{
+    return exp(-sqdist(a, b, p) / theta);
+}
+
+static double dot(const double *a, const double *b, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+/* Lower Cholesky factor L (row-major n x n) of the symmetric matrix A,
+ * computed row by row: L[i][m] = (A[i][m] - sum_{l<m} L[i][l] L[m][l]) / L[m][m]
+ * and L[i][i] = sqrt(A[i][i] - sum_{l<i} L[i][l]^2).  Returns -1 when a
+ * pivot is not positive. */
+static int cholesky(const double *A, int n, double *L)
+{
+    for (int i = 0; i < n; i++) {
+        for (int m = 0; m <= i; m++) {
+            double s = A[(size_t)i * n + m];
+            for (int l = 0; l < m; l++) s -= L[(size_t)i * n + l] * L[(size_t)m * n + l];
+            if (m == i) {
+                if (!(s > 0.0)) return -1;
+                L[(size_t)i * n + i] = sqrt(s);
+            } else {
+                L[(size_t)i * n + m] = s / L[(size_t)m * n + m];
+            }
+        }
+        for (int m = i + 1; m < n; m++) L[(size_t)i * n + m] = 0.0;
+    }
+    return 0;
+}
+
+/* Solve L w = b by forward substitution. */
+static void forward_solve(const double *L, int n, const double *b, double *w)
+{
+    for (int i = 0; i < n; i++) {
+        double s = b[i];
+        for (int l = 0; l < i; l++) s -= L[(size_t)i * n + l] * w[l];
+        w[i] = s / L[(size_t)i * n + i];
+    }
+}
+
+/* K_j = K(D, D) + eta I for the j design indices D. */
+static void design_cov(const double *X, int p, const int32_t *D, int j, double theta,
+                       double eta, double *K)
+{
+    for (int a = 0; a < j; a++) {
+        for (int b = 0; b < j; b++) {
+            K[(size_t)a * j + b] = (a == b) ? 1.0 + eta
+                                            : corr(X + (size_t)D[a] * p, X + (size_t)D[b] * p, p, theta);
+        }
+    }
+}
+
+typedef struct {
+    double d2;
+    int64_t i;
+} keyed;
+
+static int keyed_cmp(const void *pa, const void *pb)
+{
+    const keyed *a = (const keyed *)pa, *b = (const keyed *)pb;
+    if (a->d2 < b->d2) return -1;
+    if (a->d2 > b->d2) return 1;
+    return (a->i > b->i) - (a->i < b->i);
+}
+
+/* The M nearest design points of x, ascending by (squared distance, index)
+ * (Section 3: nearest-neighbour sub-design; Section 6: N' nearest candidates). */
+int lagp_oracle_knn(const double *X, int64_t N, int32_t p, const double *x, int64_t M,
+                    int32_t *idx, double *d2_out)
+{
+    if (N < 1 || p < 1 || M < 1 || M > N) return ORACLE_EINVAL;
+    keyed *all = (keyed *)malloc((size_t)N * sizeof(keyed));
+    if (!all) return ORACLE_ENOMEM;
+    for (int64_t i = 0; i < N; i++) {
+        all[i].d2 = sqdist(X + (size_t)i * p, x, p);
+        all[i].i = i;
+    }
+    qsort(all, (size_t)N, sizeof(keyed), keyed_cmp);
+    for (int64_t m = 0; m < M; m++) {
+        idx[m] = (int32_t)all[m].i;
+        if (d2_out) d2_out[m] = all[m].d2;
+    }
+    free(all);
+    return ORACLE_OK;
+}
+
+/* Local GP prediction at x from the design indices D (eqs predgp, preds2),
+ * through a fresh Cholesky factor of K_n.  out = {mean, s2, var, v_n(x), psi}. */
+int lagp_oracle_predict(const double *X, const double *y, int32_t p, const double *x,
+                        const int32_t *D, int32_t n, double theta, double eta, double *out)
+{
+    if (n < 1) return ORACLE_EINVAL;
+    double *K = (double *)malloc((size_t)n * n * sizeof(double));
+    double *L = (double *)malloc((size_t)n * n * sizeof(double));
+    double *kx = (double *)malloc((size_t)n * sizeof(double));
+    double *wx = (double *)malloc((size_t)n * sizeof(double));
+    double *yd = (double *)malloc((size_t)n * sizeof(double));
+    double *u = (double *)malloc((size_t)n * sizeof(double));
+    int rc = ORACLE_OK;
+    if (!K || !L || !kx || !wx || !yd || !u) { rc = ORACLE_ENOMEM; goto done; }
+    design_cov(X, p, D, n, theta, eta, K);
+    if (cholesky(K, n, L) != 0) {
+        for (int i = 0; i < 5; i++) out[i] = NAN;
+        rc = ORACLE_NOTPD;
+        goto done;
+    }
+    for (int a = 0; a < n; a++) {
+        kx[a] = corr(X + (size_t)D[a] * p, x, p, theta);
+        yd[a] = y[D[a]];
+    }
+    forward_solve(L, n, kx, wx);   /* wx = L^{-1} k_n(x) */
+    forward_solve(L, n, yd, u);    /* u  = L^{-1} Y_n    */
+    {
+        double mean = dot(wx, u, n);            /* k' K^{-1} Y   */
+        double psi = dot(u, u, n);              /* Y' K^{-1} Y   */
+        double vx = (1.0 + eta) - dot(wx, wx, n); /* K(x,x) - k' K^{-1} k */
+        out[0] = mean;
+        out[1] = psi * vx / n;
+        out[2] = (n > 2) ? psi * vx / (n - 2) : NAN;
+        out[3] = vx;
+        out[4] = psi;
+    }
+done:
+    free(K); free(L); free(kx); free(wx); free(yd); free(u);
+    return rc;
+}
+
+/* ALC scores of the candidates cand[0..nc-1] given the current local design
+ * D (j points): ALC(c) = cov_j(x,c)^2 / v_j(c), from a fresh Cholesky of K_j.
+ * Also returns v_j(c), cov_j(x,c) and v_j(x).  A candidate with v_j(c) <= 0
+ * scores -infinity. */
+int lagp_oracle_alc(const double *X, int32_t p, const double *x, const int32_t *D, int32_t j,
+                    const int32_t *cand, int64_t nc, double theta, double eta,
+                    double *alc, double *vc_out, double *cov_out, double *vx_out)
+{
+    if (j < 1) return ORACLE_EINVAL;
+    double *K = (double *)malloc((size_t)j * j * sizeof(double));
+    double *L = (double *)malloc((size_t)j * j * sizeof(double));
+    double *kx = (double *)malloc((size_t)j * sizeof(double));
+    double *wx = (double *)malloc((size_t)j * sizeof(double));
+    double *kc = (double *)malloc((size_t)j * sizeof(double));
+    double *wc = (double *)malloc((size_t)j * sizeof(double));
+    int rc = ORACLE_OK;
+    if (!K || !L || !kx || !wx || !kc || !wc) { rc = ORACLE_ENOMEM; goto done; }
+    design_cov(X, p, D, j, theta, eta, K);
+    if (cholesky(K, j, L) != 0) { rc = ORACLE_NOTPD; goto done; }
+    for (int a = 0; a < j; a++) kx[a] = corr(X + (size_t)D[a] * p, x, p, theta);
+    forward_solve(L, j, kx, wx);
+    if (vx_out) *vx_out = (1.0 + eta) - dot(wx, wx, j);
+    for (int64_t ci = 0; ci < nc; ci++) {
+        const double *xc = X + (size_t)cand[ci] * p;
+        for (int a = 0; a < j; a++) kc[a] = corr(X + (size_t)D[a] * p, xc, p, theta);
+        forward_solve(L, j, kc, wc);
+        double vc = (1.0 + eta) - dot(wc, wc, j);
+        double cov = corr(x, xc, p, theta) - dot(wx, wc, j);
+        alc[ci] = (vc > 0.0) ? cov * cov / vc : -INFINITY;
+        if (vc_out) vc_out[ci] = vc;
+        if (cov_out) cov_out[ci] = cov;
+    }
+done:
+    free(K); free(L); free(kx); free(wx); free(kc); free(wc);
+    return rc;
+}
+
+/* v_j(x) for the design D, from a fresh Cholesky of K_j (eq newv). */
+static int variance_at(const double *X, int p, const double *x, const int32_t *D, int j,
+                       double theta, double eta, double *K, double *L, double *kx,
+                       double *wx, double *out)
+{
+    design_cov(X, p, D, j, theta, eta, K);
+    if (cholesky(K, j, L) != 0) return ORACLE_NOTPD;
+    for (int a = 0; a < j; a++) kx[a] = corr(X + (size_t)D[a] * p, x, p, theta);
+    forward_solve(L, j, kx, wx);
+    *out = (1.0 + eta) - dot(wx, wx, j);
+    return ORACLE_OK;
+}
+
+/* Brute-force ALC: v_j(x) - v_{j+1}(x | c), each variance from its own fresh
+ * Cholesky factor (K_j, then K_{j+1} with c appended).  Non-positive-definite
+ * augmented matrices score NaN. */
+int lagp_oracle_alc_brute(const double *X, int32_t p, const double *x, const int32_t *D,
+                          int32_t j, const int32_t *cand, int64_t nc, double theta,
+                          double eta, double *alc)
+{
+    if (j < 1) return ORACLE_EINVAL;
+    int j1 = j + 1;
+    double *K = (double *)malloc((size_t)j1 * j1 * sizeof(double));
+    double *L = (double *)malloc((size_t)j1 * j1 * sizeof(double));
+    double *kx = (double *)malloc((size_t)j1 * sizeof(double));
+    double *wx = (double *)malloc((size_t)j1 * sizeof(double));
+    int32_t *D1 = (int32_t *)malloc((size_t)j1 * sizeof(int32_t));
+    int rc = ORACLE_OK;
+    double v0;
+    if (!K || !L || !kx || !wx || !D1) { rc = ORACLE_ENOMEM; goto done; }
+    if (variance_at(X, p, x, D, j, theta, eta, K, L, kx, wx, &v0) != 0) { rc = ORACLE_NOTPD; goto done; }
+    memcpy(D1, D, (size_t)j * sizeof(int32_t));
+    for (int64_t ci = 0; ci < nc; ci++) {
+        double v1;
+        D1[j] = cand[ci];
+        if (variance_at(X, p, x, D1, j1, theta, eta, K, L, kx, wx, &v1) != 0)
+            alc[ci] = NAN;
+        else
+            alc[ci] = v0 - v1;
+    }
+done:
+    free(K); free(L); free(kx); free(wx); free(D1);
+    return rc;
+}
+
+/* Greedy ALC local design and prediction at one location x.
+ *
+ *   sel[0..n-1]   chosen design indices in order (the first n0 are the
+ *                 nearest neighbours in (distance, index) order);
+ *   out[0..4]     {mean, s2, var, v_n(x), psi};
+ *   diag[3*j..]   for each greedy step j >= n0: {largest ALC, second largest
+ *                 ALC, ALC of the chosen candidate}; NaN for the n0 initial
+ *                 steps (nullable);
+ *   replay        if non-NULL, the n indices to follow instead of the
+ *                 argmax (the first n0 must be the nearest neighbours);
+ *                 diag then reports how far each followed choice falls short
+ *                 of the oracle's own largest ALC.
+ *
+ * Returns ORACLE_OK, ORACLE_NOTPD (outputs NaN) or a negative error. */
+int lagp_oracle_local(const double *X, const double *y, int64_t N, int32_t p, const double *x,
+                      int32_t n0, int32_t n, int64_t M, double theta, double eta,
+                      const int32_t *replay, int32_t *sel, double *out, double *diag)
+{
+    if (N < 1 || p < 1 || n0 < 1 || n0 > n || (int64_t)n > M || M > N || !(theta > 0.0) ||
+        !(eta >= 0.0))
+        return ORACLE_EINVAL;
+    int32_t *C = (int32_t *)malloc((size_t)M * sizeof(int32_t));
+    char *used = (char *)calloc((size_t)M, 1);
+    double *K = (double *)malloc((size_t)n * n * sizeof(double));
+    double *L = (double *)malloc((size_t)n * n * sizeof(double));
+    double *kx = (double *)malloc((size_t)n * sizeof(double));
+    double *wx = (double *)malloc((size_t)n * sizeof(double));
+    double *kc = (double *)malloc((size_t)n * sizeof(double));
+    double *wc = (double *)malloc((size_t)n * sizeof(double));
+    int rc = ORACLE_OK;
+    if (!C || !used || !K || !L || !kx || !wx || !kc || !wc) { rc = ORACLE_ENOMEM; goto done; }
+    rc = lagp_oracle_knn(X, N, p, x, M, C, NULL);
+    if (rc != ORACLE_OK) goto done;
+
+    for (int j = 0; j < n0; j++) {
+        if (replay && replay[j] != C[j]) { rc = ORACLE_EINVAL; goto done; }
+        sel[j] = C[j];
+        used[j] = 1;
+        if (diag) diag[3 * j] = diag[3 * j + 1] = diag[3 * j + 2] = NAN;
+    }
+
+    for (int j = n0; j < n; j++) {
+        /* K_j and its Cholesky factor, from scratch. */
+        design_cov(X, p, sel, j, theta, eta, K);
+        if (cholesky(K, j, L) != 0) { rc = ORACLE_NOTPD; break; }
+        for (int a = 0; a < j; a++) kx[a] = corr(X + (size_t)sel[a] * p, x, p, theta);
+        forward_solve(L, j, kx, wx);
+
+        double a1 = -INFINITY, a2 = -INFINITY, a_follow = NAN;
+        int64_t best = -1, follow = -1;
+        for (int64_t ci = 0; ci < M; ci++) {
+            if (used[ci]) continue;
+            const double *xc = X + (size_t)C[ci] * p;
+            for (int a = 0; a < j; a++) kc[a] = corr(X + (size_t)sel[a] * p, xc, p, theta);
+            forward_solve(L, j, kc, wc);
+            double vc = (1.0 + eta) - dot(wc, wc, j);
+            double cov = corr(x, xc, p, theta) - dot(wx, wc, j);
+            double alc = (vc > 0.0) ? cov * cov / vc : -INFINITY;
+            if (best < 0 || alc > a1 || (alc == a1 && C[ci] < C[best])) {
+                a2 = a1;
+                a1 = alc;
+                best = ci;
+            } else if (alc > a2) {
+                a2 = alc;
+            }
+            if (replay && C[ci] == replay[j]) { follow = ci; a_follow = alc; }
+        }
+        if (best < 0 || a1 == -INFINITY) { rc = ORACLE_NOTPD; break; }
+        int64_t take = best;
+        if (replay) {
+            if (follow < 0) { rc = ORACLE_EINVAL; goto done; }
+            take = follow;
+        }
+        if (diag) {
+            diag[3 * j] = a1;
+            diag[3 * j + 1] = a2;
+            diag[3 * j + 2] = replay ? a_follow : a1;
+        }
+        sel[j] = C[take];
+        used[take] = 1;
+    }
+
+    if (rc == ORACLE_OK) rc = lagp_oracle_predict(X, y, p, x, sel, n, theta, eta, out);
+    if (rc == ORACLE_NOTPD) {
+        for (int i = 0; i < 5; i++) out[i] = NAN;
+    }
+done:
+    free(C); free(used); free(K); free(L); free(kx); free(wx); free(kc); free(wc);
+    return rc;
+}
+
+/* Independent local designs over T predictive locations (Section 4.1),
+ * parallel over locations with OpenMP.  n_per / M_per (nullable) override
+ * n / M per location; sel is T x sel_stride.  out5 is T x 5 as in
+ * lagp_oracle_local.  status[t] receives each location's return code.
+ * Returns the first negative error, else 0. */
+int lagp_oracle_batch(const double *X, const double *y, int64_t N, int32_t p, const double *XX,
+                      int64_t T, int32_t n0, int32_t n, int64_t M, const int32_t *n_per,
+                      const int32_t *M_per, double theta, double eta, int32_t *sel,
+                      int64_t sel_stride, double *out5, int32_t *status, int32_t nthreads)
+{
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int64_t t = 0; t < T; t++) {
+        int32_t nt = n_per ? n_per[t] : n;
+        int64_t Mt = M_per ? M_per[t] : M;
+        int rc = lagp_oracle_local(X, y, N, p, XX + (size_t)t * p, n0, nt, Mt, theta, eta, NULL,
+                                   sel + (size_t)t * sel_stride, out5 + (size_t)t * 5, NULL);
+        status[t] = rc;
+        if (rc < 0) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            err = rc;
+        }
+    }
+    (void)nthreads;
+    return err;
+}
+
+int lagp_oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
