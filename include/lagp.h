@@ -1,0 +1,140 @@
+/*
+ * lagp.h -- C ABI of the MI355X local approximate Gaussian-process library.
+ *
+ * The library implements the data-parallel hot path of Gramacy & Apley,
+ * "Local Gaussian process approximation for large computer experiments":
+ * for each predictive location x it
+ *   (1) takes the n0 nearest design points as the starting local design and
+ *       the N' nearest design points as the candidate set (Section 3 and the
+ *       N' restriction of Section 6);
+ *   (2) grows the local design greedily to n points, each step adding the
+ *       candidate with the largest reduction in predictive variance at x
+ *       (the ALC criterion, eq dxy, Sections 3.2-3.3; partial-correlation form
+ *       eq dxy2, SM Section 4), with the O(j^2) partitioned-inverse update of
+ *       SM Section 1 carried in Cholesky (whitened) form;
+ *   (3) returns the local Student-t predictive mean, scale, degrees of freedom
+ *       and variance (eqs predgp and preds2 with N -> n, Section 2).
+ * Locations are independent (Section 4.1); a call processes a whole batch.
+ *
+ * Model: zero-mean GP with isotropic Gaussian correlation
+ * K(a,b) = exp(-||a-b||^2 / d) between distinct points and nugget g added to
+ * the diagonal of the local design covariance and to the self-covariance of
+ * x and of each candidate (Section 2).  Cross-covariances carry no nugget.
+ *
+ * Conventions for every entry point:
+ *   - Indices are 0-based int32 design-row indices.  N < 2^31.
+ *   - Matrices are row-major: X is N x p, XX is T x p, sel is T x sel_stride.
+ *   - Unless a flag says otherwise, array arguments of lagp_predict /
+ *     lagp_knn are DEVICE pointers on the current HIP device; the caller owns
+ *     them.  Work is enqueued on `stream` (a hipStream_t, NULL = default
+ *     stream) and outputs are valid once that stream has been synchronised.
+ *   - Argument errors are detected synchronously, before any launch, and
+ *     return LAGP_E_INVAL; lagp_last_error() then describes the problem.
+ *   - A location whose local covariance stops being positive definite (a
+ *     pivot v_j(x_s) <= 0) gets status LAGP_LOC_NOTPD, NaN outputs and -1 for
+ *     its unfilled design slots; other locations are unaffected and the call
+ *     still returns LAGP_OK.
+ *   - Calls that share one lagp_design share its workspace: issue them from
+ *     one host thread on one stream (or serialise them).
+ */
+#ifndef LAGP_H
+#define LAGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAGP_OK = 0,
+    LAGP_E_INVAL = -1,    /* bad argument (sizes, pointers, parameters)         */
+    LAGP_E_NOMEM = -2,    /* device allocation for the design or workspace failed */
+    LAGP_E_NODEVICE = -3, /* no HIP device is visible                          */
+    LAGP_E_HIP = -4,      /* a HIP runtime call failed                          */
+    LAGP_E_BUDGET = -5,   /* request larger than the serving memory budget      */
+    LAGP_E_NOTPD = -6     /* strict mode only: some location was not positive definite */
+} lagp_status;
+
+/* Per-location status codes written to the optional `status` output. */
+enum { LAGP_LOC_OK = 0, LAGP_LOC_NOTPD = 1 };
+
+/* Precision of the ALC scoring contraction.  The variance v_j(c), covariance
+ * cov_j(x,c), the factor update and the final prediction are FP64 in every
+ * mode. */
+typedef enum {
+    LAGP_PREC_FP64 = 0,        /* everything FP64                               */
+    LAGP_PREC_SCORE_FP32 = 1   /* whitened candidate tile stored and contracted in FP32 */
+} lagp_precision;
+
+/* Flags. */
+#define LAGP_PTR_HOST 1u   /* lagp_design_create: X and y are host pointers        */
+#define LAGP_STRICT 2u     /* lagp_predict: return LAGP_E_NOTPD if any location failed */
+
+typedef struct {
+    int32_t n0;        /* starting nearest-neighbour design size, 1 <= n0 <= n     */
+    int32_t n;         /* final local design size, n <= ncand                     */
+    int32_t ncand;     /* candidate-set size N' (nearest design points), <= N     */
+    double d;          /* lengthscale theta > 0                                    */
+    double g;          /* nugget eta >= 0                                          */
+    int32_t precision; /* lagp_precision                                           */
+    uint32_t flags;    /* LAGP_STRICT                                              */
+} lagp_params;
+
+typedef struct lagp_design lagp_design;
+
+/* Copy a design (X: N x p row-major, y: N) to the current device in the
+ * layouts the kernels read (coordinate-major and row-major copies).  X and y
+ * are device pointers unless flags has LAGP_PTR_HOST.  The caller keeps
+ * ownership of X and y; the design owns its copies until
+ * lagp_design_destroy.  Section 2: the design D = (X, Y). */
+int lagp_design_create(const double *X, const double *y, int64_t N, int32_t p, uint32_t flags,
+                       void *stream, lagp_design **out);
+
+/* Free the design and its workspace.  NULL is ignored. */
+void lagp_design_destroy(lagp_design *design);
+
+/* Candidate sets (Section 3 nearest neighbours; Section 6 N' restriction):
+ * for each of the T locations XX (device, T x p), write the indices of its M
+ * nearest design points, ordered by (squared distance, index), into
+ * idx[t * idx_stride + m] (device int32).  Squared distances are summed over
+ * coordinates left to right without fused multiply-add. */
+int lagp_knn(const lagp_design *design, const double *XX, int64_t T, int32_t M, int32_t *idx,
+             int64_t idx_stride, void *stream);
+
+/* Greedy ALC local designs and local GP prediction for T locations.
+ *   XX        device T x p predictive locations;
+ *   n_per     optional device int32[T]: per-location n (overrides params->n);
+ *   ncand_per optional device int32[T]: per-location N' (overrides params->ncand);
+ *   mean, s2  device double[T]: predictive mean k'K^{-1}Y and Student-t scale
+ *             psi * v_n(x) / n (eqs predgp, preds2);
+ *   df        optional device int32[T]: degrees of freedom n;
+ *   var       optional device double[T]: variance psi * v_n(x) / (n-2) (NaN if n <= 2);
+ *   sel       optional device int32 T x sel_stride: chosen design indices in
+ *             selection order (first n0 are the nearest neighbours);
+ *   status    optional device int8[T]: LAGP_LOC_OK / LAGP_LOC_NOTPD.
+ * Requires 1 <= n0 <= n <= ncand <= N for every location; sel_stride >= max n. */
+int lagp_predict(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
+                 const int32_t *n_per, const int32_t *ncand_per, double *mean, double *s2,
+                 int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
+                 void *stream);
+
+/* Device bytes of workspace lagp_predict needs for a batch of T locations
+ * with the given maxima (for admission control by callers). */
+int lagp_workspace_bytes(const lagp_design *design, int64_t T, int32_t nmax, int32_t ncand_max,
+                         size_t *out);
+
+/* Number of HIP devices visible (0 when none); never fails. */
+int lagp_device_count(void);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char *lagp_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int lagp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAGP_H */

@@ -1,0 +1,194 @@
+"""Python binding of liblagp (include/lagp.h): local approximate GP
+prediction with greedy ALC local designs on MI355X.
+
+The functions named ``lagp_*`` mirror the C entry points one to one and only
+marshal arguments: torch tensors on the GPU pass their data pointers and the
+current HIP stream.  Every step of the computation runs in the library's HIP
+kernels.  Importing this module fails if the library has not been built
+(``python -m paper_1303_0383_amd.build`` or ``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblagp.so")
+
+LAGP_OK, LAGP_E_INVAL, LAGP_E_NOMEM, LAGP_E_NODEVICE, LAGP_E_HIP, LAGP_E_BUDGET, LAGP_E_NOTPD = 0, -1, -2, -3, -4, -5, -6
+LAGP_LOC_OK, LAGP_LOC_NOTPD = 0, 1
+LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32 = 0, 1
+LAGP_PTR_HOST, LAGP_STRICT = 1, 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python -m paper_1303_0383_amd.build)")
+
+_lib = C.CDLL(LIB_PATH)
+
+
+class lagp_params(C.Structure):
+    _fields_ = [("n0", C.c_int32), ("n", C.c_int32), ("ncand", C.c_int32), ("d", C.c_double),
+                ("g", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+_P = C.c_void_p
+_lib.lagp_design_create.argtypes = [_P, _P, C.c_int64, C.c_int32, C.c_uint32, _P, C.POINTER(_P)]
+_lib.lagp_design_destroy.argtypes = [_P]
+_lib.lagp_design_destroy.restype = None
+_lib.lagp_knn.argtypes = [_P, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]
+_lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P,
+                              C.c_int64, _P, _P]
+_lib.lagp_workspace_bytes.argtypes = [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+_lib.lagp_last_error.restype = C.c_char_p
+for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
+           "lagp_version"):
+    getattr(_lib, _f).restype = C.c_int
+
+
+class LagpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lagp error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> int:
+    if rc != LAGP_OK:
+        raise LagpError(rc, lagp_last_error())
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ----------------------------------------------------------- C entry points
+def lagp_version() -> int:
+    return _lib.lagp_version()
+
+
+def lagp_device_count() -> int:
+    return _lib.lagp_device_count()
+
+
+def lagp_last_error() -> str:
+    return _lib.lagp_last_error().decode()
+
+
+def lagp_design_create(X, y, stream=None):
+    """Copy the design (X: N x p float64, y: N) to the device.
+
+    X, y may be CUDA tensors or host numpy arrays / CPU tensors."""
+    import torch
+    host = isinstance(X, np.ndarray) or (hasattr(X, "is_cuda") and not X.is_cuda)
+    if host:
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
+        flags = LAGP_PTR_HOST
+        s = None if not torch.cuda.is_available() else _stream(stream)
+    else:
+        X = X.contiguous()
+        y = y.contiguous()
+        flags = 0
+        s = _stream(stream)
+    N, p = X.shape
+    out = _P()
+    _check(_lib.lagp_design_create(_ptr(X), _ptr(y), N, p, flags, s, C.byref(out)))
+    return out
+
+
+def lagp_design_destroy(design) -> None:
+    _lib.lagp_design_destroy(design)
+
+
+def lagp_knn(design, XX, T: int, M: int, idx, idx_stride: int, stream=None) -> None:
+    _check(_lib.lagp_knn(design, _ptr(XX), T, M, _ptr(idx), idx_stride, _stream(stream)))
+
+
+def lagp_predict(design, XX, T: int, params: lagp_params, n_per, ncand_per, mean, s2, df, var, sel,
+                 sel_stride: int, status, stream=None) -> None:
+    _check(_lib.lagp_predict(design, _ptr(XX), T, C.byref(params), _ptr(n_per), _ptr(ncand_per), _ptr(mean),
+                             _ptr(s2), _ptr(df), _ptr(var), _ptr(sel), sel_stride, _ptr(status),
+                             _stream(stream)))
+
+
+def lagp_workspace_bytes(design, T: int, nmax: int, ncand_max: int) -> int:
+    out = C.c_size_t()
+    _check(_lib.lagp_workspace_bytes(design, T, nmax, ncand_max, C.byref(out)))
+    return int(out.value)
+
+
+# ------------------------------------------------------- tensor conveniences
+@dataclass
+class Prediction:
+    mean: "torch.Tensor"
+    s2: "torch.Tensor"
+    df: "torch.Tensor"
+    var: "torch.Tensor"
+    sel: "torch.Tensor"
+    status: "torch.Tensor"
+
+
+class Design:
+    """Owns a lagp_design; frees it on close() or garbage collection."""
+
+    def __init__(self, X, y, stream=None):
+        self.N, self.p = int(X.shape[0]), int(X.shape[1])
+        self._h = lagp_design_create(X, y, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lagp_design_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def knn(self, XX, M: int, stream=None):
+        import torch
+        XX = XX.contiguous()
+        idx = torch.empty((XX.shape[0], M), dtype=torch.int32, device=XX.device)
+        lagp_knn(self._h, XX, XX.shape[0], M, idx, M, stream)
+        return idx
+
+    def predict(self, XX, n0: int, n: int, ncand: int, d: float, g: float, n_per=None, ncand_per=None,
+                precision: int = LAGP_PREC_FP64, strict: bool = False, out: Optional[Prediction] = None,
+                stream=None) -> Prediction:
+        import torch
+        XX = XX.contiguous()
+        T = XX.shape[0]
+        dev = XX.device
+        nmax = int(n_per.max().item()) if (n_per is not None and T) else n
+        if out is None:
+            out = Prediction(mean=torch.empty(T, dtype=torch.float64, device=dev),
+                             s2=torch.empty(T, dtype=torch.float64, device=dev),
+                             df=torch.empty(T, dtype=torch.int32, device=dev),
+                             var=torch.empty(T, dtype=torch.float64, device=dev),
+                             sel=torch.empty((T, max(nmax, 1)), dtype=torch.int32, device=dev),
+                             status=torch.empty(T, dtype=torch.int8, device=dev))
+        prm = lagp_params(n0, n, ncand, d, g, precision, LAGP_STRICT if strict else 0)
+        lagp_predict(self._h, XX, T, prm, n_per, ncand_per, out.mean, out.s2, out.df, out.var, out.sel,
+                     out.sel.shape[1], out.status, stream)
+        return out

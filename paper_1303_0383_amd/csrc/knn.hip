@@ -1,0 +1,523 @@
+// knn.hip -- exact brute-force nearest-neighbour candidate sets for gfx950.
+//
+// For every predictive location x_t the M design points with the smallest
+// (squared distance, index) keys are selected (the nearest-neighbour
+// sub-design of Section 3 and the N' nearest candidates of Section 6).
+//
+// Key: a 96-bit integer (bits of the non-negative FP64 squared distance) << 31
+// | design index.  Non-negative doubles order like their bit patterns, so the
+// integer order is exactly the (distance, index) order and every key is
+// unique.  The M-th smallest key is found by radix refinement of a key window:
+//
+//   pass 0   64 bins over the binary exponent of d^2 (octaves 2^-51..2^11,
+//            clamped at both ends);
+//   pass k   64 equal bins over the current window;
+// until the window holds at most BUCKET_MAX keys (or one key).  A collect
+// pass then writes every key below the window straight to the output and the
+// keys inside the window to a small per-location bucket, which a finalise
+// kernel sorts to fill the remaining slots.
+//
+// Mapping: one thread per location, 256 locations per block.  The block
+// streams the design through an LDS tile (coalesced loads of the
+// coordinate-major copy) and every thread reads each tile point at a
+// wave-uniform LDS address (a broadcast).  Histograms are private per thread
+// in LDS, so no atomics are needed inside a block.  The design range can be
+// split over gridDim.y blocks to fill the chip when T is small; partial
+// histograms then meet in global memory through atomics.
+//
+// Squared distances are summed over coordinates left to right with no fused
+// multiply-add (this file is compiled with -ffp-contract=off).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lagp_internal.h"
+
+namespace lagp {
+
+typedef unsigned __int128 u128;
+
+#define KNN_THREADS 256
+#define KNN_BINS 64
+#define KNN_TILE 256
+
+struct KnnState {
+    uint64_t lo_hi, lo_lo;   // window lower bound (128-bit key)
+    uint64_t hi_hi, hi_lo;   // window upper bound, exclusive
+    uint32_t below;          // keys strictly below lo
+    uint32_t bucket;         // keys inside the window (valid once settled)
+    int32_t settled;         // 1: window final
+    int32_t pass;            // passes run so far
+};
+
+__device__ __forceinline__ u128 mk128(uint64_t h, uint64_t l) { return ((u128)h << 64) | l; }
+__device__ __forceinline__ uint64_t hi64(u128 v) { return (uint64_t)(v >> 64); }
+__device__ __forceinline__ uint64_t lo64(u128 v) { return (uint64_t)v; }
+
+__device__ __forceinline__ int ceil_log2_128(u128 w)
+{
+    // smallest s with 2^s >= w (w >= 1)
+    u128 v = w - 1;
+    int s = 0;
+    while (v) { v >>= 1; ++s; }
+    return s;
+}
+
+// Squared distance of an LDS tile point to x, left to right.  P > 0 is the
+// dimension known at compile time (x in registers); P == 0 reads a runtime
+// dimension p with x kept in LDS.
+template <int P>
+__device__ __forceinline__ double tile_d2(const double* __restrict__ pt, const double* x, int p)
+{
+    double s = 0.0;
+    if (P > 0) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double t = pt[k] - x[k];
+            s += t * t;
+        }
+    } else {
+        for (int k = 0; k < p; ++k) {
+            double t = pt[k] - x[k * KNN_THREADS];
+            s += t * t;
+        }
+    }
+    return s;
+}
+
+// Pass 0 bin of a squared distance: its octave, clamped to [2^-51, 2^11).
+__device__ __forceinline__ int exp_bin(uint64_t bits)
+{
+    int e = (int)(bits >> 52) - 971;
+    return e < 0 ? 0 : (e > 63 ? 63 : e);
+}
+
+// Key window of pass 0 bin b.
+__device__ __forceinline__ void exp_bin_window(int b, u128* lo, u128* hi)
+{
+    const u128 top = (u128)1 << 94;
+    *lo = (b == 0) ? (u128)0 : ((u128)(uint64_t)(b + 971) << 83);
+    *hi = (b == 63) ? top : ((u128)(uint64_t)(b + 972) << 83);
+}
+
+__global__ void knn_init_kernel(KnnState* st, uint32_t* hist, int64_t T)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    KnnState s;
+    s.lo_hi = s.lo_lo = 0;
+    s.hi_hi = (uint64_t)1 << 30;  // 2^94
+    s.hi_lo = 0;
+    s.below = 0;
+    s.bucket = 0;
+    s.settled = 0;
+    s.pass = 0;
+    st[t] = s;
+    for (int b = 0; b < KNN_BINS; ++b) hist[t * KNN_BINS + b] = 0;
+}
+
+// Load one tile of design points (coordinate-major source) into LDS as
+// point-major rows of p doubles.
+__device__ __forceinline__ void load_tile(double* tile, const double* __restrict__ Xsoa, int64_t N,
+                                          int p, int64_t base, int count)
+{
+    for (int k = 0; k < p; ++k)
+        for (int i = threadIdx.x; i < count; i += KNN_THREADS)
+            tile[i * p + k] = Xsoa[(int64_t)k * N + base + i];
+}
+
+// One histogram pass over design rows [i0, i1) for the 256 locations of this
+// block.  Pass kind is taken per location from its state.
+template <int P>
+__global__ void __launch_bounds__(KNN_THREADS)
+knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double* __restrict__ XX,
+                int64_t T, int32_t M, KnnState* __restrict__ st, uint32_t* __restrict__ hist,
+                int64_t chunk)
+{
+    extern __shared__ double smem[];
+    double* tile = smem;                                          // KNN_TILE * p
+    uint16_t* h = (uint16_t*)(tile + (size_t)KNN_TILE * p);       // KNN_BINS * KNN_THREADS
+    __shared__ int any_active;
+
+    const int tid = threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * KNN_THREADS + tid;
+    const int64_t i0 = (int64_t)blockIdx.y * chunk;
+    const int64_t i1 = (i0 + chunk < N) ? i0 + chunk : N;
+
+    bool active = false;
+    int kind = 0;
+    u128 lo = 0, hi = 0;
+    int shift = 0;
+    double xr[P > 0 ? P : 1];
+    double* xl = (double*)(h + KNN_BINS * KNN_THREADS) + tid;  // P == 0: x in LDS (8-byte aligned: 64*256*2 bytes)
+    const double* x = P > 0 ? xr : xl;
+    if (t < T) {
+        KnnState s = st[t];
+        active = !s.settled;
+        kind = s.pass == 0 ? 0 : 1;
+        lo = mk128(s.lo_hi, s.lo_lo);
+        hi = mk128(s.hi_hi, s.hi_lo);
+        shift = ceil_log2_128(hi - lo) - 6;
+        if (shift < 0) shift = 0;
+        if (P > 0) {
+#pragma unroll
+            for (int k = 0; k < (P > 0 ? P : 1); ++k) xr[k] = XX[t * p + k];
+        } else {
+            for (int k = 0; k < p; ++k) xl[k * KNN_THREADS] = XX[t * p + k];
+        }
+    }
+    if (tid == 0) any_active = 0;
+    __syncthreads();
+    if (active) any_active = 1;
+    __syncthreads();
+    if (!any_active) return;
+
+    for (int b = 0; b < KNN_BINS; ++b) h[b * KNN_THREADS + tid] = 0;
+    // (a split holds fewer than 65536 design rows, so 16-bit counters suffice)
+    const uint64_t lo_d = (uint64_t)(lo >> 31);
+    const uint64_t hi_d = (uint64_t)((hi - 1) >> 31);
+
+    for (int64_t base = i0; base < i1; base += KNN_TILE) {
+        const int count = (int)((i1 - base) < KNN_TILE ? (i1 - base) : KNN_TILE);
+        __syncthreads();
+        load_tile(tile, Xsoa, N, p, base, count);
+        __syncthreads();
+        if (!active) continue;
+        if (kind == 0) {
+            for (int ii = 0; ii < count; ++ii) {
+                double d2 = tile_d2<P>(tile + ii * p, x, p);
+                int b = exp_bin((uint64_t)__double_as_longlong(d2));
+                h[b * KNN_THREADS + tid] += 1;
+            }
+        } else {
+            for (int ii = 0; ii < count; ++ii) {
+                double d2 = tile_d2<P>(tile + ii * p, x, p);
+                uint64_t bits = (uint64_t)__double_as_longlong(d2);
+                if (bits < lo_d || bits > hi_d) continue;
+                u128 key = ((u128)bits << 31) | (uint64_t)(base + ii);
+                if (key < lo || key >= hi) continue;
+                int b = (int)((key - lo) >> shift);
+                h[b * KNN_THREADS + tid] += 1;
+            }
+        }
+    }
+    if (active) {
+        uint32_t* hg = hist + t * KNN_BINS;
+        for (int b = 0; b < KNN_BINS; ++b) {
+            uint32_t c = h[b * KNN_THREADS + tid];
+            if (c) {
+                if (gridDim.y == 1) hg[b] += c;
+                else atomicAdd(hg + b, c);
+            }
+        }
+    }
+}
+
+// Choose the bin holding the M-th key; settle or narrow the window.
+__global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, int64_t T, int32_t M_all,
+                                  const int32_t* __restrict__ M_per, int32_t bucket_max, uint32_t* unsettled)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int32_t M = M_per ? M_per[t] : M_all;
+    KnnState s = st[t];
+    if (s.settled) return;
+    uint32_t* hg = hist + t * KNN_BINS;
+    uint32_t cum = s.below;
+    int b = 0;
+    for (; b < KNN_BINS - 1; ++b) {
+        if (cum + hg[b] >= (uint32_t)M) break;
+        cum += hg[b];
+    }
+    uint32_t inbin = hg[b];
+    u128 lo, hi;
+    if (s.pass == 0) {
+        exp_bin_window(b, &lo, &hi);
+    } else {
+        u128 olo = mk128(s.lo_hi, s.lo_lo), ohi = mk128(s.hi_hi, s.hi_lo);
+        int shift = ceil_log2_128(ohi - olo) - 6;
+        if (shift < 0) shift = 0;
+        lo = olo + ((u128)(uint64_t)b << shift);
+        hi = lo + ((u128)1 << shift);
+        if (hi > ohi) hi = ohi;
+    }
+    s.lo_hi = hi64(lo); s.lo_lo = lo64(lo);
+    s.hi_hi = hi64(hi); s.hi_lo = lo64(hi);
+    s.below = cum;
+    s.bucket = inbin;
+    s.pass += 1;
+    s.settled = (inbin <= (uint32_t)bucket_max) || (hi - lo <= 1);
+    st[t] = s;
+    for (int k = 0; k < KNN_BINS; ++k) hg[k] = 0;
+    if (!s.settled) atomicAdd(unsettled, 1u);
+}
+
+// Collect: keys below the window go straight to idx[t][*]; keys inside the
+// window go to the bucket with their full key.
+template <int P>
+__global__ void __launch_bounds__(KNN_THREADS)
+knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double* __restrict__ XX,
+                   int64_t T, const KnnState* __restrict__ st, uint32_t* __restrict__ counts,
+                   int32_t* __restrict__ idx, int64_t idx_stride, uint64_t* __restrict__ bucket,
+                   int32_t bucket_max, int64_t chunk)
+{
+    extern __shared__ double smem[];
+    double* tile = smem;
+    const int tid = threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * KNN_THREADS + tid;
+    const int64_t i0 = (int64_t)blockIdx.y * chunk;
+    const int64_t i1 = (i0 + chunk < N) ? i0 + chunk : N;
+    const bool split = gridDim.y > 1;
+
+    bool active = t < T;
+    u128 lo = 0, hi = 0;
+    double xr[P > 0 ? P : 1];
+    double* xl = tile + (size_t)KNN_TILE * p + tid;  // P == 0: x in LDS
+    const double* x = P > 0 ? xr : xl;
+    uint32_t nbelow = 0, nbkt = 0;
+    if (active) {
+        KnnState s = st[t];
+        lo = mk128(s.lo_hi, s.lo_lo);
+        hi = mk128(s.hi_hi, s.hi_lo);
+        if (P > 0) {
+#pragma unroll
+            for (int k = 0; k < (P > 0 ? P : 1); ++k) xr[k] = XX[t * p + k];
+        } else {
+            for (int k = 0; k < p; ++k) xl[k * KNN_THREADS] = XX[t * p + k];
+        }
+    }
+    const uint64_t lo_d = (uint64_t)(lo >> 31);
+    const uint64_t hi_d = (uint64_t)((hi - 1) >> 31);
+    int32_t* out = active ? idx + t * idx_stride : nullptr;
+    uint64_t* bk = active ? bucket + t * (int64_t)bucket_max * 2 : nullptr;
+
+    for (int64_t base = i0; base < i1; base += KNN_TILE) {
+        const int count = (int)((i1 - base) < KNN_TILE ? (i1 - base) : KNN_TILE);
+        __syncthreads();
+        load_tile(tile, Xsoa, N, p, base, count);
+        __syncthreads();
+        if (!active) continue;
+        for (int ii = 0; ii < count; ++ii) {
+            double d2 = tile_d2<P>(tile + ii * p, x, p);
+            uint64_t bits = (uint64_t)__double_as_longlong(d2);
+            if (bits > hi_d) continue;
+            const int64_t gi = base + ii;
+            u128 key = ((u128)bits << 31) | (uint64_t)gi;
+            if (bits < lo_d || key < lo) {
+                uint32_t slot = split ? atomicAdd(counts + 2 * t, 1u) : nbelow++;
+                out[slot] = (int32_t)gi;
+            } else if (key < hi) {
+                uint32_t slot = split ? atomicAdd(counts + 2 * t + 1, 1u) : nbkt++;
+                if (slot < (uint32_t)bucket_max) {
+                    bk[2 * slot] = hi64(key);
+                    bk[2 * slot + 1] = lo64(key);
+                }
+            }
+        }
+    }
+    if (!split && active) {
+        counts[2 * t] = nbelow;
+        counts[2 * t + 1] = nbkt;
+    }
+}
+
+// Sort each location's bucket (at most bucket_max keys, bucket_max a power of
+// two <= 1024) and append its smallest M - below keys.  One block per location.
+__global__ void __launch_bounds__(KNN_THREADS)
+knn_finalize_kernel(int64_t T, int32_t M_all, const int32_t* __restrict__ M_per, const KnnState* __restrict__ st,
+                    const uint32_t* __restrict__ counts, int32_t* __restrict__ idx,
+                    int64_t idx_stride, const uint64_t* __restrict__ bucket, int32_t bucket_max,
+                    int32_t* __restrict__ bad)
+{
+    __shared__ uint64_t kh[1024], kl[1024];
+    const int64_t t = blockIdx.x;
+    if (t >= T) return;
+    const int32_t M = M_per ? M_per[t] : M_all;
+    const KnnState s = st[t];
+    const uint32_t nb = counts[2 * t], nk = counts[2 * t + 1];
+    const int tid = threadIdx.x;
+    if (nb != s.below || nk != s.bucket || nb + nk < (uint32_t)M || nk > (uint32_t)bucket_max) {
+        if (tid == 0) atomicAdd(bad, 1);
+        return;
+    }
+    const uint64_t* bk = bucket + t * (int64_t)bucket_max * 2;
+    int P = 1;
+    while (P < (int)nk) P <<= 1;
+    for (int e = tid; e < P; e += KNN_THREADS) {
+        if (e < (int)nk) { kh[e] = bk[2 * e]; kl[e] = bk[2 * e + 1]; }
+        else { kh[e] = ~0ull; kl[e] = ~0ull; }
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = tid; e < P; e += KNN_THREADS) {
+                int partner = e ^ stride;
+                if (partner > e) {
+                    bool up = (e & size) == 0;
+                    u128 a = mk128(kh[e], kl[e]), b = mk128(kh[partner], kl[partner]);
+                    if ((a > b) == up) {
+                        kh[e] = hi64(b); kl[e] = lo64(b);
+                        kh[partner] = hi64(a); kl[partner] = lo64(a);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int need = M - (int)nb;
+    int32_t* out = idx + t * idx_stride + nb;
+    for (int e = tid; e < need; e += KNN_THREADS)
+        out[e] = (int32_t)(kl[e] & 0x7fffffffull);
+}
+
+// Sort a location's M indices by (squared distance, index): used only when a
+// caller asks for ordered candidate lists.  One block per location, M <= 4096.
+__global__ void __launch_bounds__(KNN_THREADS)
+knn_sort_kernel(const double* __restrict__ Xaos, int p, const double* __restrict__ XX, int64_t T,
+                int32_t M, int32_t* __restrict__ idx, int64_t idx_stride)
+{
+    __shared__ uint64_t kh[4096];
+    __shared__ uint32_t ki[4096];
+    const int64_t t = blockIdx.x;
+    if (t >= T) return;
+    const int tid = threadIdx.x;
+    int32_t* row = idx + t * idx_stride;
+    const double* x = XX + t * p;
+    int P = 1;
+    while (P < M) P <<= 1;
+    for (int e = tid; e < P; e += KNN_THREADS) {
+        if (e < M) {
+            int32_t i = row[e];
+            const double* xi = Xaos + (int64_t)i * p;
+            double s = 0.0;
+            for (int k = 0; k < p; ++k) {
+                double d = xi[k] - x[k];
+                s += d * d;
+            }
+            kh[e] = (uint64_t)__double_as_longlong(s);
+            ki[e] = (uint32_t)i;
+        } else {
+            kh[e] = ~0ull;
+            ki[e] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = tid; e < P; e += KNN_THREADS) {
+                int partner = e ^ stride;
+                if (partner > e) {
+                    bool up = (e & size) == 0;
+                    bool gt = kh[e] > kh[partner] || (kh[e] == kh[partner] && ki[e] > ki[partner]);
+                    if (gt == up) {
+                        uint64_t th = kh[e]; kh[e] = kh[partner]; kh[partner] = th;
+                        uint32_t ti = ki[e]; ki[e] = ki[partner]; ki[partner] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < M; e += KNN_THREADS) row[e] = (int32_t)ki[e];
+}
+
+// ---------------------------------------------------------------- launcher
+size_t knn_workspace_bytes(int64_t T, int32_t bucket_max)
+{
+    size_t b = 0;
+    b += align256((size_t)T * sizeof(KnnState));
+    b += align256((size_t)T * KNN_BINS * sizeof(uint32_t));
+    b += align256((size_t)T * 2 * sizeof(uint32_t));
+    b += align256((size_t)T * bucket_max * 2 * sizeof(uint64_t));
+    b += align256(4 * sizeof(uint32_t));
+    return b;
+}
+
+int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const int32_t* M_per,
+            int32_t* idx, int64_t idx_stride, bool sorted, void* ws, size_t ws_bytes, hipStream_t stream,
+            int num_cu, size_t max_lds, std::string* err)
+{
+    if (T == 0) return 0;
+    const int32_t bucket_max = 512;
+    if (ws_bytes < knn_workspace_bytes(T, bucket_max)) { *err = "knn workspace too small"; return -1; }
+    char* w = (char*)ws;
+    KnnState* st = (KnnState*)w; w += align256((size_t)T * sizeof(KnnState));
+    uint32_t* hist = (uint32_t*)w; w += align256((size_t)T * KNN_BINS * sizeof(uint32_t));
+    uint32_t* counts = (uint32_t*)w; w += align256((size_t)T * 2 * sizeof(uint32_t));
+    uint64_t* bucket = (uint64_t*)w; w += align256((size_t)T * bucket_max * 2 * sizeof(uint64_t));
+    uint32_t* flags = (uint32_t*)w;  // [0] unsettled, [1] bad
+
+    const int64_t nblk = (T + KNN_THREADS - 1) / KNN_THREADS;
+    // Split the design over gridDim.y so that the grid covers the chip about
+    // four times over, keeping at least 2 tiles per split.
+    int64_t split = (4LL * num_cu + nblk - 1) / nblk;
+    int64_t max_split = (D.N + 2 * KNN_TILE - 1) / (2 * KNN_TILE);
+    if (split > max_split) split = max_split;
+    if (split < 1) split = 1;
+    if (split > 65535) split = 65535;
+    // 16-bit private histogram counters: at most 65280 design rows per split.
+    const int64_t max_chunk = 65280;
+    if (split < (D.N + max_chunk - 1) / max_chunk) split = (D.N + max_chunk - 1) / max_chunk;
+    int64_t chunk = (D.N + split - 1) / split;
+    chunk = (chunk + KNN_TILE - 1) / KNN_TILE * KNN_TILE;
+    split = (D.N + chunk - 1) / chunk;
+
+    const size_t lds_x = D.p <= 8 ? 0 : (size_t)KNN_THREADS * D.p * sizeof(double);
+    const size_t lds_hist = (size_t)KNN_TILE * D.p * sizeof(double) + (size_t)KNN_BINS * KNN_THREADS * 2 + lds_x;
+    const size_t lds_coll = (size_t)KNN_TILE * D.p * sizeof(double) + lds_x;
+    if (lds_hist > max_lds) { *err = "input dimension too large for the kNN tile"; return -1; }
+#define LAGP_KNN_ATTR(PP)                                                                              \
+    if (hipFuncSetAttribute((const void*)knn_hist_kernel<PP>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)lds_hist) != hipSuccess ||                                            \
+        hipFuncSetAttribute((const void*)knn_collect_kernel<PP>,                                       \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_coll) != hipSuccess) { \
+        *err = "cannot reserve LDS for the kNN kernels";                                              \
+        return -2;                                                                                     \
+    }
+    LAGP_DISPATCH_P(D.p, LAGP_KNN_ATTR);
+#undef LAGP_KNN_ATTR
+
+    hipLaunchKernelGGL(knn_init_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st, hist, T);
+    if (hipMemsetAsync(flags, 0, 16, stream) != hipSuccess) { *err = "hipMemsetAsync failed"; return -2; }
+    const dim3 grid((unsigned)nblk, (unsigned)split);
+    for (int pass = 0; pass < 20; ++pass) {
+#define LAGP_KNN_HIST(PP) hipLaunchKernelGGL(knn_hist_kernel<PP>, grid, dim3(KNN_THREADS), lds_hist, stream, \
+                                             D.Xsoa, D.N, D.p, XX, T, M, st, hist, chunk)
+        LAGP_DISPATCH_P(D.p, LAGP_KNN_HIST);
+#undef LAGP_KNN_HIST
+        if (hipMemsetAsync(flags, 0, 4, stream) != hipSuccess) { *err = "hipMemsetAsync failed"; return -2; }
+        hipLaunchKernelGGL(knn_decide_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st,
+                           hist, T, M, M_per, bucket_max, flags);
+        uint32_t unsettled = 0;
+        if (hipMemcpyAsync(&unsettled, flags, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            *err = "knn pass synchronisation failed";
+            return -2;
+        }
+        if (unsettled == 0) break;
+    }
+    if (hipMemsetAsync(counts, 0, (size_t)T * 2 * sizeof(uint32_t), stream) != hipSuccess) {
+        *err = "hipMemsetAsync failed";
+        return -2;
+    }
+#define LAGP_KNN_COLL(PP) hipLaunchKernelGGL(knn_collect_kernel<PP>, grid, dim3(KNN_THREADS), lds_coll, stream, \
+                                             D.Xsoa, D.N, D.p, XX, T, st, counts, idx, idx_stride, bucket, \
+                                             bucket_max, chunk)
+    LAGP_DISPATCH_P(D.p, LAGP_KNN_COLL);
+#undef LAGP_KNN_COLL
+    hipLaunchKernelGGL(knn_finalize_kernel, dim3((unsigned)T), dim3(KNN_THREADS), 0, stream, T, M, M_per, st, counts,
+                       idx, idx_stride, bucket, bucket_max, (int32_t*)(flags + 1));
+    if (sorted)
+        hipLaunchKernelGGL(knn_sort_kernel, dim3((unsigned)T), dim3(KNN_THREADS), 0, stream, D.Xaos, D.p, XX,
+                           T, M, idx, idx_stride);
+    uint32_t bad = 0;
+    if (hipMemcpyAsync(&bad, flags + 1, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        *err = "knn synchronisation failed";
+        return -2;
+    }
+    if (bad) { *err = "knn selection inconsistent"; return -3; }
+    if (hipGetLastError() != hipSuccess) { *err = "knn launch failed"; return -2; }
+    return 0;
+}
+
+}  // namespace lagp

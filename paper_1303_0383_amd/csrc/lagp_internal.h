@@ -1,0 +1,86 @@
+// lagp_internal.h -- declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace lagp {
+
+// Device-resident design: coordinate-major copy for streaming scans and a
+// row-major copy for gathers of single rows.
+struct DeviceDesign {
+    const double* Xsoa = nullptr;  // p x N
+    const double* Xaos = nullptr;  // N x p
+    const double* y = nullptr;     // N
+    int64_t N = 0;
+    int32_t p = 0;
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Dispatch a macro on the input dimension: compile-time 1..8, runtime otherwise.
+#define LAGP_DISPATCH_P(pval, MACRO) \
+    switch (pval) {                  \
+    case 1: MACRO(1); break;         \
+    case 2: MACRO(2); break;         \
+    case 3: MACRO(3); break;         \
+    case 4: MACRO(4); break;         \
+    case 5: MACRO(5); break;         \
+    case 6: MACRO(6); break;         \
+    case 7: MACRO(7); break;         \
+    case 8: MACRO(8); break;         \
+    default: MACRO(0); break;        \
+    }
+
+// ---- nearest neighbours (knn.hip)
+size_t knn_workspace_bytes(int64_t T, int32_t bucket_max);
+// Returns 0, or <0 with *err set.  Row t of idx receives the M (or M_per[t])
+// nearest design rows, unordered unless `sorted` (uniform M only).
+int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const int32_t* M_per,
+            int32_t* idx, int64_t idx_stride, bool sorted, void* ws, size_t ws_bytes, hipStream_t stream,
+            int num_cu, size_t max_lds, std::string* err);
+
+// ---- greedy local design + prediction (design.hip)
+struct DesignLaunch {
+    // inputs
+    const double* XX = nullptr;  // T x p
+    int64_t T = 0;
+    const int32_t* cand = nullptr;  // T x cand_stride (unordered candidate sets)
+    int64_t cand_stride = 0;
+    const int32_t* n_per = nullptr;
+    const int32_t* M_per = nullptr;
+    int32_t n0 = 0, n = 0, M = 0;  // uniform values (maxima when per-location arrays are given)
+    double theta = 1.0, eta = 0.0;
+    int32_t precision = 0;
+    // outputs
+    double* mean = nullptr;
+    double* s2 = nullptr;
+    int32_t* df = nullptr;
+    double* var = nullptr;
+    int32_t* sel = nullptr;
+    int64_t sel_stride = 0;
+    int8_t* status = nullptr;
+};
+
+struct DesignPlan {
+    int cpt = 0;           // candidate slots per thread
+    int rreg = 0;          // register-resident tile rows
+    int rlds = 0;          // LDS-resident tile rows
+    int rglob = 0;         // global-resident tile rows
+    bool coords_lds = false;
+    int blocks = 0;        // persistent grid size
+    size_t lds_bytes = 0;
+    size_t scratch_per_block = 0;  // bytes of global scratch per block
+    size_t counter_bytes = 0;
+};
+
+int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
+                int num_cu, size_t max_lds, DesignPlan* plan, std::string* err);
+size_t design_workspace_bytes(const DesignPlan& plan);
+int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& plan, void* ws,
+               size_t ws_bytes, hipStream_t stream, std::string* err);
+
+}  // namespace lagp

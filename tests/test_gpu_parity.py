@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from parity import compare, gpu_predict
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="session")
+def lagp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_1303_0383_amd as L   # raises if the HIP library is missing
+    return L
+
+
+@pytest.fixture(scope="session")
+def c0(lagp):
+    w = workloads.c0()
+    return w, lagp.Design(w.X, w.y)
+
+
+@pytest.fixture(scope="session")
+def c1(lagp):
+    w = workloads.c1()
+    return w, lagp.Design(w.X, w.y)
+
+
+@pytest.fixture(scope="session")
+def c2(lagp):
+    w = workloads.c2(T=100000)
+    return w, lagp.Design(w.X, w.y)
+
+
+def _knn_gpu(design, XX, M):
+    import torch
+    XXd = torch.as_tensor(XX, device="cuda:0")
+    idx = design.knn(XXd, M)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy()
+
+
+# ------------------------------------------------------------------ kNN
+@pytest.mark.parametrize("M", [1, 6, 50, 999, 1000])
+def test_knn_c0_exact(c0, M):
+    w, D = c0
+    idx = _knn_gpu(D, w.XX, M)
+    for t in range(w.T):
+        ref, _ = oracle.knn(w.X, w.XX[t], M)
+        assert np.array_equal(idx[t], ref), t
+
+
+def test_knn_c1_exact(c1):
+    w, D = c1
+    sub = np.arange(0, w.T, 97)
+    idx = _knn_gpu(D, w.XX[sub], w.ncand)
+    for k, t in enumerate(sub):
+        ref, _ = oracle.knn(w.X, w.XX[t], w.ncand)
+        assert np.array_equal(idx[k], ref), t
+
+
+def test_knn_c2_exact(c2):
+    w, D = c2
+    sub = np.arange(0, 300)
+    idx = _knn_gpu(D, w.XX[sub], 2000)
+    for k in range(0, 300, 7):
+        ref, _ = oracle.knn(w.X, w.XX[sub[k]], 2000)
+        assert np.array_equal(idx[k], ref), k
+
+
+def test_knn_ties_grid(lagp):
+    # A regular grid design has many exactly equal distances: ties go by index.
+    g = np.linspace(-1, 1, 21)
+    X = np.stack(np.meshgrid(g, g), -1).reshape(-1, 2)
+    D = lagp.Design(X, np.zeros(len(X)))
+    XX = np.array([[0.0, 0.0], [0.05, 0.05], [0.1, 0.0], [1.0, 1.0]])
+    for M in (5, 13, 60, 441):
+        idx = _knn_gpu(D, XX, M)
+        for t in range(len(XX)):
+            ref, _ = oracle.knn(X, XX[t], M)
+            assert np.array_equal(idx[t], ref), (M, t)
+
+
+# ------------------------------------------------------------- predict
+def test_predict_c0_full(c0):
+    w, D = c0
+    res = gpu_predict(D, w.XX, w.n0, w.n, w.ncand, w.d, w.g)
+    summary = compare(w.X, w.y, w.XX, w.n0, w.n, w.ncand, w.d, w.g, res)
+    print("c0", summary)
+    assert summary["identical"] + summary["replayed"] == w.T
+
+
+def test_predict_c1_subset(c1):
+    w, D = c1
+    sub = np.arange(0, w.T, 37)                       # 271 locations over the grid
+    XX = w.XX[sub]
+    res = gpu_predict(D, XX, w.n0, w.n, w.ncand, w.d, w.g)
+    summary = compare(w.X, w.y, XX, w.n0, w.n, w.ncand, w.d, w.g, res)
+    print("c1", summary)
+
+
+@pytest.mark.parametrize("n", [50, 64])
+def test_predict_c2_subset(c2, n):
+    w, D = c2
+    XX = w.XX[:300]
+    res = gpu_predict(D, XX, w.n0, n, w.ncand, w.d, w.g)
+    summary = compare(w.X, w.y, XX, w.n0, n, w.ncand, w.d, w.g, res, idx=range(0, 300, 10))
+    print("c2 n=%d" % n, summary)
+
+
+def test_predict_c2_full_size_sampled(c2):
+    """The headline launch configuration (N=100k, T=100k, n=50), sampled."""
+    w, D = c2
+    res = gpu_predict(D, w.XX, w.n0, 50, w.ncand, w.d, w.g)
+    assert np.all(res["status"] == 0)
+    assert np.all(np.isfinite(res["mean"])) and np.all(res["s2"] > 0)
+    sample = np.random.default_rng(5).choice(w.T, 24, replace=False)
+    summary = compare(w.X, w.y, w.XX, w.n0, 50, w.ncand, w.d, w.g, res, idx=sample)
+    print("c2 full sampled", summary)
+
+
+def test_predict_uneven_sizes(c2):
+    w, D = c2
+    r = np.random.default_rng(11)
+    T = 40
+    XX = w.XX[1000:1000 + T]
+    n_per = r.integers(16, 129, T).astype(np.int32)
+    M_per = (256 * r.integers(1, 17, T)).astype(np.int32)
+    res = gpu_predict(D, XX, w.n0, int(n_per.max()), int(M_per.max()), w.d, w.g, n_per=n_per, M_per=M_per)
+    summary = compare(w.X, w.y, XX, w.n0, 0, 0, w.d, w.g, res, idx=range(0, T, 3), n_per=n_per, M_per=M_per)
+    print("uneven", summary)
+
+
+# ------------------------------------------------------------ edge cases
+def test_empty_batch(c0):
+    import torch
+    w, D = c0
+    out = D.predict(torch.empty((0, 2), dtype=torch.float64, device="cuda:0"), 6, 50, 1000, 0.5, 1e-6)
+    assert out.mean.numel() == 0
+
+
+@pytest.mark.parametrize("T", [1, 255, 257, 513])
+def test_ragged_batches(c1, T):
+    w, D = c1
+    XX = w.XX[3:3 + T]
+    res = gpu_predict(D, XX, w.n0, 20, 200, w.d, w.g)
+    compare(w.X, w.y, XX, w.n0, 20, 200, w.d, w.g, res, idx=sorted({0, T // 2, T - 1}))
+
+
+def test_n_equals_n0_is_nn_kriging(c1):
+    w, D = c1
+    XX = w.XX[:64]
+    res = gpu_predict(D, XX, 12, 12, 40, w.d, w.g)
+    compare(w.X, w.y, XX, 12, 12, 40, w.d, w.g, res)
+
+
+def test_n_equals_ncand(c0):
+    w, D = c0
+    XX = w.XX[:10]
+    res = gpu_predict(D, XX, 3, 30, 30, w.d, w.g)
+    compare(w.X, w.y, XX, 3, 30, 30, w.d, w.g, res)
+
+
+@pytest.mark.parametrize("p", [1, 3, 5, 12])
+def test_other_dimensions(lagp, p):
+    r = np.random.default_rng(100 + p)
+    X = r.uniform(0, 1, (3000, p))
+    y = np.sin(X @ r.standard_normal(p))
+    XX = r.uniform(0, 1, (40, p))
+    D = lagp.Design(X, y)
+    res = gpu_predict(D, XX, 4, 24, 300, 0.5 * p, 1e-4)
+    compare(X, y, XX, 4, 24, 300, 0.5 * p, 1e-4, res)
+    idx = _knn_gpu(D, XX, 300)
+    for t in range(0, 40, 9):
+        assert np.array_equal(idx[t], oracle.knn(X, XX[t], 300)[0])
+
+
+def test_small_n_variance(c0):
+    w, D = c0
+    res = gpu_predict(D, w.XX[:5], 1, 2, 10, w.d, w.g)
+    assert np.all(np.isnan(res["var"])) and np.all(res["s2"] > 0)
+    compare(w.X, w.y, w.XX[:5], 1, 2, 10, w.d, w.g, res)
+
+
+def test_notpd_duplicates(lagp):
+    # Duplicate rows with zero nugget: the starting design is singular.
+    X = np.repeat(np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [1.0, 1.0]]), 3, axis=0)
+    X = np.vstack([X, np.random.default_rng(1).uniform(2, 3, (40, 2))])
+    y = np.arange(len(X), dtype=np.float64)
+    D = lagp.Design(X, y)
+    XX = np.array([[0.01, 0.0], [2.5, 2.5]])
+    res = gpu_predict(D, XX, 2, 4, 10, 0.5, 0.0)
+    assert res["status"][0] == 1 and np.isnan(res["mean"][0])
+    rc, _, _, _ = oracle.local(X, y, XX[0], 2, 4, 10, 0.5, 0.0)
+    assert rc == oracle.NOTPD
+
+
+def test_alone_equals_in_batch(c1):
+    """A location's result does not depend on the rest of the batch."""
+    w, D = c1
+    XX = w.XX[:300]
+    full = gpu_predict(D, XX, w.n0, w.n, w.ncand, w.d, w.g)
+    for t in (0, 150, 299):
+        one = gpu_predict(D, XX[t:t + 1], w.n0, w.n, w.ncand, w.d, w.g)
+        assert np.array_equal(one["sel"][0], full["sel"][t])
+        assert one["mean"][0] == full["mean"][t] and one["s2"][0] == full["s2"][t]
+    perm = np.random.default_rng(2).permutation(300)
+    pr = gpu_predict(D, XX[perm], w.n0, w.n, w.ncand, w.d, w.g)
+    assert np.array_equal(pr["mean"], full["mean"][perm])
+    assert np.array_equal(pr["sel"], full["sel"][perm])
+
+
+def test_invalid_arguments(c0, lagp):
+    import torch
+    w, D = c0
+    XX = torch.as_tensor(w.XX[:4], device="cuda:0")
+    bad = [dict(n0=0, n=10, ncand=20), dict(n0=5, n=4, ncand=20), dict(n0=2, n=30, ncand=20),
+           dict(n0=2, n=10, ncand=1001), dict(n0=2, n=10, ncand=20, d=0.0), dict(n0=2, n=10, ncand=20, g=-1.0)]
+    for b in bad:
+        kw = dict(d=0.5, g=1e-6)
+        kw.update(b)
+        with pytest.raises(lagp.LagpError) as e:
+            D.predict(XX, kw["n0"], kw["n"], kw["ncand"], kw["d"], kw["g"])
+        assert e.value.code == lagp.LAGP_E_INVAL
+    with pytest.raises(lagp.LagpError):
+        D.predict(torch.as_tensor(w.XX[:4]), 2, 10, 20, 0.5, 1e-6)   # host tensor
