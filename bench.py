@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: predictive locations per second of greedy ALC local
+GP prediction on one MI355X.
+
+A step is one full lagp_predict call over the batch: exact kNN candidate
+sets, greedy ALC local designs and local predictions for every location,
+with the design and the locations already resident in HBM.  The default
+workload is the headline case N = 100,000 design points in [0,1]^8
+(sinusoid-sum response + noise), T = 100,000 uniform locations, n0 = 8,
+n = 50, N' = 2000 candidates, d = 1.0, g = 1e-4.
+
+Printed: one JSON line (metric, value, roofline of the greedy-design kernel
+from live HIP-event timing, CPU oracle baseline on a bounded sample, and a
+parity summary of that sample against the GPU outputs).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "predictive locations/sec (n=50, N=100k) at stated accuracy; p50/p99 request latency"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def design_flops(n: int, M: int, p: int, n0: int) -> int:
+    """Algorithmic FP64 flops of the greedy-design kernel for one location.
+
+    Gather: M squared distances to x (3p - 1 flops) and one division by d.
+    Step i = 0 .. n-2 (row i of the whitened tile) for each of the M - i - 1
+    live candidates: K(s,c) distance and scaling (3p flops), the dot
+    product with the chosen column (2i), the division by delta (1), the
+    variance and covariance updates (2 + 2), and from step n0-1 on the ALC
+    score cov^2 / v (2).  Exponentials are counted separately (see
+    design_exps)."""
+    f = M * 3 * p
+    for i in range(n - 1):
+        live = M - i - 1
+        f += live * (3 * p + 2 * i + 5 + (2 if i + 1 >= n0 else 0))
+    return f
+
+
+def design_exps(n: int, M: int) -> int:
+    return M + sum(M - i - 1 for i in range(n - 1))
+
+
+def workload(name: str, T: int | None):
+    import workloads
+    if name == "c2_n50":
+        w = workloads.c2(n=50)
+    elif name == "c2":
+        w = workloads.c2(n=64)
+    elif name == "c1":
+        w = workloads.c1()
+    elif name == "c0":
+        w = workloads.c0()
+    elif name == "c3":
+        w = workloads.c3()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    if T is not None and T < w.T:
+        w = w.subset(np.arange(T))
+    return w
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2_n50", choices=["c2_n50", "c2", "c1", "c0", "c3"])
+    ap.add_argument("--T", type=int, default=None, help="use only the first T locations")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="locations in the CPU oracle sample (0: skip)")
+    ap.add_argument("--parity-sample", type=int, default=64, help="sampled locations checked against the oracle")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(locations are independent, so the multi-GPU form is a partition of the batch).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1303_0383_amd as lagp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = workload(args.workload, args.T)
+    prec = lagp.LAGP_PREC_FP64 if args.precision == "fp64" else lagp.LAGP_PREC_SCORE_FP32
+    D = lagp.Design(w.X, w.y)
+    XX = torch.as_tensor(w.XX, device=dev)
+    n_per = None if w.n_per is None else torch.as_tensor(w.n_per, device=dev)
+    M_per = None if w.ncand_per is None else torch.as_tensor(w.ncand_per, device=dev)
+    nmax = int(w.n_per.max()) if w.n_per is not None else w.n
+    Mmax = int(w.ncand_per.max()) if w.ncand_per is not None else w.ncand
+    T = w.T
+    out = lagp.Prediction(mean=torch.empty(T, dtype=torch.float64, device=dev),
+                          s2=torch.empty(T, dtype=torch.float64, device=dev),
+                          df=torch.empty(T, dtype=torch.int32, device=dev),
+                          var=torch.empty(T, dtype=torch.float64, device=dev),
+                          sel=torch.empty((T, nmax), dtype=torch.int32, device=dev),
+                          status=torch.empty(T, dtype=torch.int8, device=dev))
+
+    def step():
+        D.predict(XX, w.n0, nmax, Mmax, w.d, w.g, n_per=n_per, ncand_per=M_per, precision=prec, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lagp.lagp_timing_enable(D.handle, True)
+    lagp.lagp_phase_times(D.handle)
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+    lagp.lagp_timing_enable(D.handle, False)
+
+    value = T * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # Roofline of the dominant kernel (greedy design): algorithmic FP64 flops per launch
+    # over its average launch duration from HIP events on the launch stream.
+    if w.n_per is not None:
+        flops = sum(design_flops(int(a), int(b), w.p, w.n0) for a, b in zip(w.n_per, w.ncand_per))
+        exps = sum(design_exps(int(a), int(b)) for a, b in zip(w.n_per, w.ncand_per))
+    else:
+        flops = T * design_flops(w.n, w.ncand, w.p, w.n0)
+        exps = T * design_exps(w.n, w.ncand)
+    chunks = max(1, -(-T // (1 << 17)))
+    per_launch_flops = flops / chunks
+    avg_launch_s = des_ms / max(launches, 1) / 1e3
+    achieved = per_launch_flops / avg_launch_s / 1e12
+    roofline = {"kernel": "design_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
+                "flops_per_launch": per_launch_flops, "exps_per_launch": exps / chunks,
+                "exp_rate_G_per_s": round(exps / chunks / avg_launch_s / 1e9, 2)}
+    traffic_file = os.path.join(ROOT, "profiles", f"design_kernel_{args.workload}_traffic.txt")
+    if os.path.exists(traffic_file) and args.precision == "fp64":
+        for line in open(traffic_file):
+            if line.startswith("bytes_per_launch:"):
+                roofline["traffic"] = float(line.split(":")[1])
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "locations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32-tile", "data": "synthetic",
+        "config": {"workload": args.workload, "N": w.N, "p": w.p, "T": T, "n0": w.n0, "n": nmax,
+                   "ncand": Mmax, "d": w.d, "g": w.g, "uneven": w.n_per is not None},
+        "phase_ms_per_step": {"knn": round(knn_ms / args.steps, 3), "design": round(des_ms / args.steps, 3)},
+        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),
+        "roofline": roofline,
+    }
+
+    res = {k: getattr(out, k).cpu().numpy() for k in ("mean", "s2", "df", "var", "sel", "status")}
+    rng = np.random.default_rng(20130383)
+
+    # Parity of sampled outputs against the FP64 oracle.
+    if args.parity_sample > 0:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import compare
+        idx = np.sort(rng.choice(T, min(args.parity_sample, T), replace=False))
+        try:
+            summ = compare(w.X, w.y, w.XX, w.n0, w.n, w.ncand, w.d, w.g, res, idx=idx,
+                           n_per=w.n_per, M_per=w.ncand_per)
+            result["parity"] = {"locations": len(idx), "ok": True,
+                                **{k: (float(f"{v:.3e}") if isinstance(v, float) else v) for k, v in summ.items()}}
+        except AssertionError as e:
+            result["parity"] = {"locations": len(idx), "ok": False, "error": str(e)}
+
+    # CPU baseline: the oracle, as it stands, on a bounded sample of the same workload.
+    if args.cpu_sample > 0:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        idx = np.sort(rng.choice(T, min(args.cpu_sample, T), replace=False))
+        sub = w.subset(idx)
+        tc = time.perf_counter()
+        oracle.batch(sub.X, sub.y, sub.XX, sub.n0, sub.n, sub.ncand, sub.d, sub.g, n_per=sub.n_per,
+                     M_per=sub.ncand_per, threads=threads)
+        cpu_s = time.perf_counter() - tc
+        result["cpu_baseline"] = {"value": round(len(idx) / cpu_s, 2), "unit": "locations/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"{len(idx)} seeded locations of the same workload, {cpu_s:.1f} s, "
+                                            f"OpenMP over locations"}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -125,6 +125,14 @@ int lagp_predict(const lagp_design *design, const double *XX, int64_t T, const l
 int lagp_workspace_bytes(const lagp_design *design, int64_t T, int32_t nmax, int32_t ncand_max,
                          size_t *out);
 
+/* Per-phase device timing.  While enabled, lagp_predict records HIP events on
+ * its stream around each launch of its two phases: the candidate-set (kNN)
+ * kernels and the greedy-design kernel.  lagp_phase_times waits for the
+ * recorded events, returns the summed milliseconds and the number of
+ * design-kernel launches since the last call, and clears the record. */
+int lagp_timing_enable(lagp_design *design, int enable);
+int lagp_phase_times(lagp_design *design, double *knn_ms, double *design_ms, int64_t *design_launches);
+
 /* Number of HIP devices visible (0 when none); never fails. */
 int lagp_device_count(void);
 

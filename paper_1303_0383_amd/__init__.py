@@ -44,9 +44,11 @@ _lib.lagp_knn.argtypes = [_P, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]
 _lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P,
                               C.c_int64, _P, _P]
 _lib.lagp_workspace_bytes.argtypes = [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+_lib.lagp_timing_enable.argtypes = [_P, C.c_int]
+_lib.lagp_phase_times.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.lagp_last_error.restype = C.c_char_p
 for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
-           "lagp_version"):
+           "lagp_version", "lagp_timing_enable", "lagp_phase_times"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -131,6 +133,17 @@ def lagp_workspace_bytes(design, T: int, nmax: int, ncand_max: int) -> int:
     out = C.c_size_t()
     _check(_lib.lagp_workspace_bytes(design, T, nmax, ncand_max, C.byref(out)))
     return int(out.value)
+
+
+def lagp_timing_enable(design, enable: bool) -> None:
+    _check(_lib.lagp_timing_enable(design, 1 if enable else 0))
+
+
+def lagp_phase_times(design):
+    """(knn_ms, design_ms, design_launches) summed since the last call."""
+    a, b, n = C.c_double(), C.c_double(), C.c_int64()
+    _check(_lib.lagp_phase_times(design, C.byref(a), C.byref(b), C.byref(n)))
+    return a.value, b.value, n.value
 
 
 # ------------------------------------------------------- tensor conveniences

@@ -34,12 +34,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lagp_internal.h"
 
 namespace lagp {
 
-#define DT 256
-#define DWAVES (DT / 64)
 
 struct DesignArgs {
     const double* Xaos;
@@ -67,6 +67,33 @@ struct DesignArgs {
     unsigned int* counter;
 };
 
+// ---- exact division helpers
+// a / b correctly rounded from y = RN(1/b): q = RN(a*y), r = a - q*b (exact
+// through the fused multiply-add), RN(q + r*y) = RN(a/b) (Markstein's
+// correction; inputs here are normal and finite).
+__device__ __forceinline__ double div_by(double a, double b, double y)
+{
+    const double q = a * y;
+    const double r = __builtin_fma(-q, b, a);
+    return __builtin_fma(r, y, q);
+}
+
+// ---- wave reductions with DPP (xor 1, xor 2 as quad permutes; rotations by
+// 4 and 8 inside each 16-lane row), then cross-row shuffles.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Candidate ordering for the argmax: larger score first, then smaller index.
 __device__ __forceinline__ bool better(double a, int ia, double b, int ib)
 {
@@ -76,6 +103,14 @@ __device__ __forceinline__ bool better(double a, int ia, double b, int ib)
 __device__ __forceinline__ bool nearer(double a, int ia, double b, int ib)
 {
     return a < b || (a == b && ia < ib);
+}
+
+// Four consecutive LDS doubles (16-byte aligned start) as two 16-byte reads.
+__device__ __forceinline__ void ld4(const double* p, double* o)
+{
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 
 template <int P>
@@ -99,39 +134,82 @@ __device__ __forceinline__ double sqdist_lds(const double* __restrict__ a, const
     return s;
 }
 
-template <int CPT, int RREG, int P>
+// Rows of the whitened tile kept in registers for a workgroup size and slot
+// count.  With 256 threads (one wave per SIMD) a lane can hold 512 registers,
+// the upper half as accumulation registers the compiler uses as spill space;
+// with 512 threads a lane has 256.
+__host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl)
+{
+    return dt == 256 ? (cpt >= 16 ? 0 : cpt == 8 ? 4 : cpt == 4 ? (cl ? 16 : 12) : cpt == 2 ? 32 : 64)
+                     : (cpt >= 4 ? 0 : cpt == 2 ? 4 : 16);
+}
+
+// Rows per prefetch block of the global part of the tile.
+__host__ __device__ constexpr int prefetch_rows(int cpt)
+{
+    return cpt >= 8 ? 1 : 8 / cpt;
+}
+
+// Combine (value, design index, slot) with a partner lane's triple.
+// MAX: larger value wins (argmax of ALC); otherwise smaller wins (nearest).
+template <bool MAX>
+__device__ __forceinline__ void pick(double& v, int& i, int& s, double ov, int oi, int os)
+{
+    const bool take = os >= 0 && (s < 0 || (MAX ? better(ov, oi, v, i) : nearer(ov, oi, v, i)));
+    if (take) { v = ov; i = oi; s = os; }
+}
+
+template <bool MAX>
+__device__ __forceinline__ void wave_pick(double& v, int& i, int& s)
+{
+    pick<MAX>(v, i, s, dpp_d<0xB1>(v), dpp_i<0xB1>(i), dpp_i<0xB1>(s));     // xor 1
+    pick<MAX>(v, i, s, dpp_d<0x4E>(v), dpp_i<0x4E>(i), dpp_i<0x4E>(s));     // xor 2
+    pick<MAX>(v, i, s, dpp_d<0x124>(v), dpp_i<0x124>(i), dpp_i<0x124>(s));  // rotate 4 in row
+    pick<MAX>(v, i, s, dpp_d<0x128>(v), dpp_i<0x128>(i), dpp_i<0x128>(s));  // rotate 8 in row
+    pick<MAX>(v, i, s, __shfl_xor(v, 16), __shfl_xor(i, 16), __shfl_xor(s, 16));
+    pick<MAX>(v, i, s, __shfl_xor(v, 32), __shfl_xor(i, 32), __shfl_xor(s, 32));
+}
+
+// DT threads per workgroup, CPT candidate slots per thread, RREG register
+// rows, P compile-time dimension (0: runtime), CL candidate coordinates in LDS.
+template <int DT, int CPT, int RREG, int P, bool CL>
 __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 {
+    constexpr int DWAVES = DT / 64;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int p = P > 0 ? P : A.p;
-    const int nmax = A.nmax;
+    const int nmax = (A.nmax + 3) & ~3;   // padded: 4-row blocks read up to 3 entries ahead
     const int Mpad = CPT * DT;
     const double theta = A.theta, eta = A.eta;
     const double one_eta = 1.0 + eta;
+    const double rtheta = 1.0 / theta;
 
     // ---- LDS carve-up (doubles first, then ints)
     double* ws = smem;               // [nmax] column of the chosen candidate
     double* wx = ws + nmax;          // [nmax] L^{-1} k(x)
     double* uu = wx + nmax;          // [nmax] L^{-1} Y
     double* xl = uu + nmax;          // [p]    predictive location
-    double* xsl = xl + p;            // [p]    chosen candidate
-    double* misc = xsl + p;          // [4]    v_s, y_s
+    double* xsl = xl + p;            // [p+1]  (spare)
+    double* misc = xsl + p + 1;      // [4]    v_s
     double* redv = misc + 4;         // [2*DWAVES] per-wave best scores
     int* redi = (int*)(redv + 2 * DWAVES);  // [2*DWAVES] best design index
     int* reds = redi + 2 * DWAVES;          // [2*DWAVES] best slot
     int* forced = reds + 2 * DWAVES;        // [nmax] slots of the nearest neighbours
-    int* ctl = forced + nmax;               // [4]  location, chosen index
+    int* ctl = forced + nmax;               // [4]  location
     size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
     off = (off + 15) & ~(size_t)15;
-    double* Xcl = (double*)((char*)smem + off);                // [p][Mpad] if coords in LDS
-    double* Wl = Xcl + (A.coords_lds ? (size_t)p * Mpad : 0);  // [rlds][Mpad]
+    double* Xcl = (double*)((char*)smem + off);              // [p+1][Mpad] when CL: coordinates, y
+    double* Wl = Xcl + (CL ? (size_t)(p + 1) * Mpad : 0);     // [rlds][Mpad]
 
     double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-    double* Wg = Xcg + (A.coords_lds ? 0 : (int64_t)p * Mpad);
-    double* Xc = A.coords_lds ? Xcl : Xcg;
+    double* Wg = Xcg + (CL ? 0 : (int64_t)(p + 1) * Mpad);
+    double* Xc = CL ? Xcl : Xcg;
     const int rlds = A.rlds;
+    const int G0 = RREG + rlds;   // first global row
+    for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = 0.0;
+    (void)xsl;
 
     for (;;) {
         if (tid == 0) ctl[0] = (int)atomicAdd(A.counter, 1u);
@@ -141,7 +219,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         const int n = A.n_per ? A.n_per[t] : A.n;
         const int M = A.M_per ? A.M_per[t] : A.M;
         const int n0 = A.n0;
+        const int32_t* cand = A.cand + t * A.cand_stride;
         for (int k = tid; k < p; k += DT) xl[k] = A.XX[t * p + k];
+        // ws, wx, uu are zero beyond the current step: padded terms subtract an exact 0.
+        for (int l = tid; l < nmax; l += DT) { ws[l] = 0.0; wx[l] = 0.0; uu[l] = 0.0; }
         if (A.sel)
             for (int i = tid; i < n; i += DT) A.sel[t * A.sel_stride + i] = -1;
         __syncthreads();
@@ -152,32 +233,37 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         }
         const double* xp = P > 0 ? xr : xl;
 
-        // ---- gather candidates; K(x,c), v_0(c) = 1 + g
+        // ---- gather candidates (coordinates and y into the coordinate block);
+        //      K(x,c) and v_0(c) = 1 + g
         int ci[CPT];
-        double yc[CPT], v[CPT], cov[CPT], d2[CPT];
+        double v[CPT], cov[CPT], d2[CPT];
         double Wr[RREG > 0 ? RREG : 1][CPT];
+#pragma unroll
+        for (int l = 0; l < (RREG > 0 ? RREG : 1); ++l)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) Wr[l][k] = 0.0;
         uint32_t chosen = 0;   // bit k: slot retired (chosen or absent)
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int slot = tid + k * DT;
             if (slot < M) {
-                const int c = A.cand[t * A.cand_stride + slot];
+                const int c = cand[slot];
                 ci[k] = c;
-                yc[k] = A.y[c];
+                Xc[(int64_t)p * Mpad + slot] = A.y[c];
                 const double* xc = A.Xaos + (int64_t)c * p;
-                double s = 0.0;
+                double sq = 0.0;
                 for (int kk = 0; kk < p; ++kk) {
                     const double ck = xc[kk];
                     Xc[(int64_t)kk * Mpad + slot] = ck;
                     const double tt = xp[kk] - ck;
-                    s += tt * tt;
+                    sq += tt * tt;
                 }
-                d2[k] = s;
-                cov[k] = exp(-s / theta);
+                d2[k] = sq;
+                cov[k] = exp(-div_by(sq, theta, rtheta));
                 v[k] = one_eta;
             } else {
                 ci[k] = 0x7fffffff;
-                yc[k] = 0.0;
+                Xc[(int64_t)p * Mpad + slot] = 0.0;
                 d2[k] = INFINITY;
                 cov[k] = 0.0;
                 v[k] = one_eta;
@@ -198,19 +284,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         bd = d2[k]; bi = ci[k]; bs = tid + k * DT;
                     }
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    double od = __shfl_xor(bd, o);
-                    int oi = __shfl_xor(bi, o), os = __shfl_xor(bs, o);
-                    if (nearer(od, oi, bd, bi)) { bd = od; bi = oi; bs = os; }
-                }
+                wave_pick<false>(bd, bi, bs);
                 const int par = (r & 1) * DWAVES;
                 if (lane == 0) { redv[par + wave] = bd; redi[par + wave] = bi; reds[par + wave] = bs; }
                 __syncthreads();
                 bd = redv[par]; bi = redi[par]; bs = reds[par];
-                for (int w = 1; w < DWAVES; ++w)
-                    if (nearer(redv[par + w], redi[par + w], bd, bi)) {
-                        bd = redv[par + w]; bi = redi[par + w]; bs = reds[par + w];
-                    }
+                for (int w = 1; w < DWAVES; ++w) pick<false>(bd, bi, bs, redv[par + w], redi[par + w], reds[par + w]);
                 if (tid == 0) forced[r] = bs;
                 if (bs >= 0 && (bs % DT) == tid) taken |= 1u << (bs / DT);
             }
@@ -225,7 +304,9 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (s < 0 || s >= M) { notpd = 1; break; }
             const int s_lane = s % DT;
             const int s_k = s / DT;
-            // Owner publishes the register part of its column, v(s), y(s).
+            // Phase A (before the barrier): the owner publishes the register
+            // part of its column and v(s); everyone copies the LDS / global
+            // part and evaluates K(s, .) for x and its own candidates.
             if (tid == s_lane) {
                 const int kk = __builtin_amdgcn_readfirstlane(s_k);
 #pragma unroll
@@ -235,82 +316,172 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
                             if (l < i) ws[l] = Wr[l][k];
                         misc[0] = v[k];
-                        misc[1] = yc[k];
-                        ctl[1] = ci[k];
                     }
                 }
                 chosen |= 1u << kk;
             }
-            // Everyone copies the LDS / global part of the column.
             for (int l = RREG + tid; l < i; l += DT)
-                ws[l] = (l < RREG + rlds) ? Wl[(int64_t)(l - RREG) * Mpad + s]
-                                          : Wg[(int64_t)(l - RREG - rlds) * Mpad + s];
-            for (int k = tid; k < p; k += DT) xsl[k] = Xc[(int64_t)k * Mpad + s];
-            __syncthreads();
-
-            const double vs = misc[0];
-            const double ys = misc[1];
-            const int cs = ctl[1];
-            if (!(vs > 0.0)) { notpd = 1; break; }
-            const double delta = sqrt(vs);
+                ws[l] = (l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s];
             double xs[P > 0 ? P : 1];
             if (P > 0) {
 #pragma unroll
-                for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = xsl[k];
+                for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
             }
-            const double* xsp = P > 0 ? xs : xsl;
+            const double ys = Xc[(int64_t)p * Mpad + s];
+            const double* xsp = P > 0 ? xs : xl;   // runtime dimension: read below from Xc
+            double ax, acc[CPT];
+            if (P > 0) {
+                ax = exp(-div_by(sqdist_lds<P>(xsp, xl, 1, p), theta, rtheta));
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    acc[k] = exp(-div_by(sqdist_lds<P>(xsp, Xc + tid + k * DT, Mpad, p), theta, rtheta));
+            } else {
+                double sqx = 0.0, sq[CPT];
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) sq[k] = 0.0;
+                for (int kk = 0; kk < p; ++kk) {
+                    const double a = Xc[(int64_t)kk * Mpad + s];
+                    const double tx = a - xl[kk];
+                    sqx += tx * tx;
+#pragma unroll
+                    for (int k = 0; k < CPT; ++k) {
+                        const double tc = a - Xc[(int64_t)kk * Mpad + tid + k * DT];
+                        sq[k] += tc * tc;
+                    }
+                }
+                ax = exp(-div_by(sqx, theta, rtheta));
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) acc[k] = exp(-div_by(sq[k], theta, rtheta));
+            }
+            (void)xsp;
 
-            // New entries of w_x and u (every thread computes the same values).
-            double ax = exp(-sqdist_lds<P>(xsp, xl, 1, p) / theta);
+            // Prefetch the first global rows.
+            constexpr int U = prefetch_rows(CPT);
+            double pre[U][CPT];
+            const int gcount = i > G0 ? i - G0 : 0;
+            if (gcount > 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (u < gcount) {
+                        const double* row = Wg + (int64_t)u * Mpad + tid;
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) pre[u][k] = row[k * DT];
+                    }
+            }
+            __syncthreads();   // B1: column of s and v(s) published
+
+            const double vs = misc[0];
+            if (!(vs > 0.0)) { notpd = 1; break; }
+            const double delta = sqrt(vs);
+            const double rdelta = 1.0 / delta;
             double ay = ys;
-            for (int l = 0; l < i; ++l) {
-                const double w = ws[l];
-                ax -= w * wx[l];
-                ay -= w * uu[l];
-            }
-            const double rx = ax / delta;
-            const double ry = ay / delta;
-            if (tid == 0) {
-                wx[i] = rx;
-                uu[i] = ry;
-                if (A.sel) A.sel[t * A.sel_stride + i] = cs;
-            }
-            if (i == n - 1) break;
-
-            // Row i of W for every live candidate.
-            double acc[CPT];
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-                const int slot = tid + k * DT;
-                acc[k] = exp(-sqdist_lds<P>(xsp, Xc + slot, Mpad, p) / theta);
-            }
-#pragma unroll
-            for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l) {
-                if (l < i) {
+            if (i == n - 1) {
+                for (int l = 0; l < i; ++l) {
                     const double w = ws[l];
+                    ax -= w * wx[l];
+                    ay -= w * uu[l];
+                }
+                if (tid == 0) {
+                    wx[i] = div_by(ax, delta, rdelta);
+                    uu[i] = div_by(ay, delta, rdelta);
+                    if (A.sel) A.sel[t * A.sel_stride + i] = cand[s];
+                }
+                break;
+            }
+
+            // Row i of W for every live candidate: acc = K(s,c) - sum_l ws[l] W[l][c].
+            // Register rows, four per block; rows >= i within a block are zero.
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) acc[k] -= w * Wr[l][k];
+            for (int l0 = 0; l0 < (RREG > 0 ? RREG : 0); l0 += 4) {
+                if (l0 < i) {
+                    double w[4], xv[4], uv[4];
+                    ld4(ws + l0, w);
+                    ld4(wx + l0, xv);
+                    ld4(uu + l0, uv);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) acc[k] -= w[r] * Wr[l0 + r][k];
+                        ax -= w[r] * xv[r];
+                        ay -= w[r] * uv[r];
+                    }
                 }
             }
             {
-                const int le = i < RREG + rlds ? i : RREG + rlds;
-                for (int l = RREG; l < le; ++l) {
-                    const double w = ws[l];
-                    const double* row = Wl + (int64_t)(l - RREG) * Mpad + tid;
+                // LDS rows [RREG, min(i, G0)), four per block.  A block may run
+                // past i (or past G0 into rows that are never written): the
+                // weight is zero there and the LDS rows hold finite values, so
+                // those terms subtract an exact 0.
+                const int le = i < G0 ? i : G0;
+                constexpr int QB = CPT >= 8 ? 1 : CPT == 4 ? 2 : 4;   // rows loaded ahead
+                for (int l0 = RREG; l0 < le; l0 += 4) {
+                    double w[4], xv[4], uv[4];
+                    ld4(ws + l0, w);
+                    ld4(wx + l0, xv);
+                    ld4(uu + l0, uv);
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) acc[k] -= w * row[k * DT];
-                }
-                for (int l = RREG + rlds; l < i; ++l) {
-                    const double w = ws[l];
-                    const double* row = Wg + (int64_t)(l - RREG - rlds) * Mpad + tid;
+                    for (int r0 = 0; r0 < 4; r0 += QB) {
+                        double q[QB][CPT];
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) acc[k] -= w * row[k * DT];
+                        for (int r = 0; r < QB; ++r) {
+                            const int lr = (l0 + r0 + r < G0) ? l0 + r0 + r : l0;   // stay inside the LDS tile
+                            const double* row = Wl + (int64_t)(lr - RREG) * Mpad + tid;
+#pragma unroll
+                            for (int k = 0; k < CPT; ++k) q[r][k] = row[k * DT];
+                        }
+#pragma unroll
+                        for (int r = 0; r < QB; ++r) {
+                            const double wr = (l0 + r0 + r < le) ? w[r0 + r] : 0.0;
+#pragma unroll
+                            for (int k = 0; k < CPT; ++k) acc[k] -= wr * q[r][k];
+                            ax -= wr * xv[r0 + r];
+                            ay -= wr * uv[r0 + r];
+                        }
+                    }
                 }
+            }
+            if (gcount > 0) {
+                // Global rows in blocks of U, the next block loaded before the
+                // current one is consumed.  Per-candidate order stays ascending.
+                int l = G0;
+                while (l < i) {
+                    const int nb = (i - l) < U ? (i - l) : U;     // rows in pre[]
+                    const int l2 = l + nb;
+                    const int nb2 = (i - l2) < U ? (i - l2) : U;   // rows of the next block
+                    double nxt[U][CPT];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (u < nb2) {
+                            const double* row = Wg + (int64_t)(l2 + u - G0) * Mpad + tid;
+#pragma unroll
+                            for (int k = 0; k < CPT; ++k) nxt[u][k] = row[k * DT];
+                        }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (u < nb) {
+                            const double w = ws[l + u];
+#pragma unroll
+                            for (int k = 0; k < CPT; ++k) acc[k] -= w * pre[u][k];
+                            ax -= w * wx[l + u];
+                            ay -= w * uu[l + u];
+                        }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) pre[u][k] = nxt[u][k];
+                    l = l2;
+                }
+            }
+            const double rx = div_by(ax, delta, rdelta);
+            if (tid == 0) {
+                wx[i] = rx;
+                uu[i] = div_by(ay, delta, rdelta);
+                if (A.sel) A.sel[t * A.sel_stride + i] = cand[s];
             }
             double r[CPT];
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
-                r[k] = acc[k] / delta;
+                r[k] = div_by(acc[k], delta, rdelta);
                 v[k] -= r[k] * r[k];
                 cov[k] -= rx * r[k];
             }
@@ -321,41 +492,41 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
                         for (int k = 0; k < CPT; ++k) Wr[l][k] = r[k];
                     }
-            } else if (i < RREG + rlds) {
+            } else if (i < G0) {
                 double* row = Wl + (int64_t)(i - RREG) * Mpad + tid;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) row[k * DT] = r[k];
             } else {
-                double* row = Wg + (int64_t)(i - RREG - rlds) * Mpad + tid;
+                double* row = Wg + (int64_t)(i - G0) * Mpad + tid;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) row[k * DT] = r[k];
             }
 
             // Argmax of ALC_{i+1} over live candidates (needed from step n0 on).
+            // The score only ranks candidates, so cov^2 / v uses a refined
+            // reciprocal of v.
             double bv = -INFINITY;
             int bi = 0x7fffffff, bs = -1;
             if (i + 1 >= n0) {
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     if (!((chosen >> k) & 1u)) {
-                        const double a = v[k] > 0.0 ? cov[k] * cov[k] / v[k] : -INFINITY;
+                        double a = -INFINITY;
+                        if (v[k] > 0.0) {
+                            double y = __builtin_amdgcn_rcp(v[k]);
+                            y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
+                            a = (cov[k] * cov[k]) * y;
+                        }
                         if (bs < 0 || better(a, ci[k], bv, bi)) { bv = a; bi = ci[k]; bs = tid + k * DT; }
                     }
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    double ov = __shfl_xor(bv, o);
-                    int oi = __shfl_xor(bi, o), os = __shfl_xor(bs, o);
-                    if (os >= 0 && (bs < 0 || better(ov, oi, bv, bi))) { bv = ov; bi = oi; bs = os; }
-                }
+                wave_pick<true>(bv, bi, bs);
                 if (lane == 0) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
             }
-            __syncthreads();
+            __syncthreads();   // B2: partial maxima published; everyone is done with ws
             if (i + 1 >= n0) {
                 bv = redv[0]; bi = redi[0]; bs = reds[0];
-                for (int w = 1; w < DWAVES; ++w)
-                    if (reds[w] >= 0 && (bs < 0 || better(redv[w], redi[w], bv, bi))) {
-                        bv = redv[w]; bi = redi[w]; bs = reds[w];
-                    }
+                for (int w = 1; w < DWAVES; ++w) pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
                 if (bs < 0 || bv == -INFINITY) { notpd = 1; break; }
                 s_next = bs;
             }
@@ -390,26 +561,23 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 }
 
 // ------------------------------------------------------------------ plan
-// Register-resident tile rows per candidate-slot count (about 180 VGPRs of tile).
-template <int CPT> struct RregFor { static constexpr int value = CPT >= 16 ? 5 : CPT == 8 ? 11 : CPT == 4 ? 22 : CPT == 2 ? 44 : 64; };
-
-static size_t fixed_lds_bytes(int nmax, int p)
+static size_t fixed_lds_bytes(int nmax, int p, int dt)
 {
+    const int dw = dt / 64;
+    nmax = (nmax + 3) & ~3;
     size_t b = 0;
-    b += (size_t)(3 * nmax + 2 * p + 4 + 2 * DWAVES) * sizeof(double);
-    b += (size_t)(4 * DWAVES + nmax + 4) * sizeof(int);
+    b += (size_t)(3 * nmax + 2 * p + 1 + 4 + 2 * dw) * sizeof(double);
+    b += (size_t)(4 * dw + nmax + 4) * sizeof(int);
     return (b + 15) & ~(size_t)15;
 }
 
-static int rreg_of(int cpt)
+// Global-memory row reads per location (in candidate rows) when rows
+// [g0, nmax-2] live in global memory: row l is read at steps l+1 .. n-2.
+static long long global_row_reads(int nmax, int g0)
 {
-    switch (cpt) {
-    case 1: return RregFor<1>::value;
-    case 2: return RregFor<2>::value;
-    case 4: return RregFor<4>::value;
-    case 8: return RregFor<8>::value;
-    default: return RregFor<16>::value;
-    }
+    long long r = 0;
+    for (int l = g0; l <= nmax - 2; ++l) r += (nmax - 2 - l);
+    return r;
 }
 
 int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
@@ -417,33 +585,45 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, i
 {
     (void)n0;
     (void)precision;
+    int dt = plan->threads == 512 ? 512 : 256;
+    if (Mmax > 2048) dt = 512;   // at most 8 slots per thread
     int cpt = 1;
-    while (cpt * DT < Mmax) cpt <<= 1;
-    if (cpt > 16) { *err = "candidate-set size above 4096 is not supported"; return -1; }
-    const int Mpad = cpt * DT;
+    while (cpt * dt < Mmax) cpt <<= 1;
+    if (cpt * dt > 4096) { *err = "candidate-set size above 4096 is not supported"; return -1; }
+    const int Mpad = cpt * dt;
     const int p = D.p;
     const int rows = nmax > 1 ? nmax - 1 : 0;  // W rows ever stored
-    const int rreg = rreg_of(cpt);
-    int rem = rows > rreg ? rows - rreg : 0;
-    const size_t fixed = fixed_lds_bytes(nmax, p);
+    const size_t fixed = fixed_lds_bytes(nmax, p, dt);
     if (fixed > max_lds) { *err = "local design size too large for LDS"; return -1; }
-    size_t avail = max_lds - fixed;
-    const size_t coord_bytes = (size_t)p * Mpad * sizeof(double);
-    bool coords_lds = coord_bytes <= avail / 2 || coord_bytes + (size_t)rem * Mpad * 8 <= avail;
-    if (coords_lds) avail -= coord_bytes;
-    int rlds = (int)(avail / ((size_t)Mpad * sizeof(double)));
-    if (rlds > rem) rlds = rem;
-    const int rglob = rem - rlds;
+    const size_t row_bytes = (size_t)Mpad * sizeof(double);
+    const int cap = (int)((max_lds - fixed) / row_bytes);   // LDS rows available
+    // Option A: coordinates in LDS.  Option B: coordinates in global memory.
+    const int pc = p + 1;   // coordinate rows plus the response
+    const int rregA = rreg_for(dt, cpt, true), rregB = rreg_for(dt, cpt, false);
+    const int remA = rows > rregA ? rows - rregA : 0, remB = rows > rregB ? rows - rregB : 0;
+    long long costA = -1, costB;
+    int rldsA = 0;
+    if (cap >= pc) {
+        rldsA = std::min(remA, cap - pc);
+        costA = global_row_reads(nmax, rregA + rldsA);
+    }
+    const int rldsB = std::min(remB, cap);
+    costB = (long long)pc * (nmax - 1) + global_row_reads(nmax, rregB + rldsB);
+    const bool cl = costA >= 0 && costA <= costB;
+    const int rlds = cl ? rldsA : rldsB;
+    const int rreg = cl ? rregA : rregB;
+    const int rem = cl ? remA : remB;
     plan->cpt = cpt;
+    plan->threads = dt;
     plan->rreg = rreg;
     plan->rlds = rlds;
-    plan->rglob = rglob;
-    plan->coords_lds = coords_lds;
-    plan->lds_bytes = fixed + (coords_lds ? coord_bytes : 0) + (size_t)rlds * Mpad * sizeof(double);
-    plan->scratch_per_block =
-        align256(((coords_lds ? 0 : (size_t)p * Mpad) + (size_t)rglob * Mpad) * sizeof(double));
+    plan->rglob = rem - rlds;
+    plan->coords_lds = cl;
+    plan->lds_bytes = fixed + (cl ? (size_t)pc * row_bytes : 0) + (size_t)rlds * row_bytes;
+    plan->scratch_per_block = align256(((cl ? 0 : (size_t)pc) + (size_t)plan->rglob) * row_bytes);
     plan->blocks = num_cu;
     plan->counter_bytes = 256;
+    plan->global_row_reads = cl ? costA : costB;
     return 0;
 }
 
@@ -452,11 +632,11 @@ size_t design_workspace_bytes(const DesignPlan& plan)
     return plan.counter_bytes + plan.scratch_per_block * (size_t)plan.blocks;
 }
 
-template <int CPT, int P>
+template <int DT, int CPT, int P, bool CL>
 static int launch_design(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    constexpr int RREG = RregFor<CPT>::value;
-    auto kern = design_kernel<CPT, RREG, P>;
+    constexpr int RREG = rreg_for(DT, CPT, CL);
+    auto kern = design_kernel<DT, CPT, RREG, P, CL>;
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)plan.lds_bytes) != hipSuccess) {
         *err = "cannot reserve LDS for the design kernel";
@@ -467,14 +647,33 @@ static int launch_design(const DesignArgs& a, const DesignPlan& plan, hipStream_
     return 0;
 }
 
-template <int CPT>
+template <int DT, int CPT, bool CL>
 static int launch_design_p(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     switch (a.p) {
-    case 2: return launch_design<CPT, 2>(a, plan, stream, err);
-    case 4: return launch_design<CPT, 4>(a, plan, stream, err);
-    case 8: return launch_design<CPT, 8>(a, plan, stream, err);
-    default: return launch_design<CPT, 0>(a, plan, stream, err);
+    case 2: return launch_design<DT, CPT, 2, CL>(a, plan, stream, err);
+    case 4: return launch_design<DT, CPT, 4, CL>(a, plan, stream, err);
+    case 8: return launch_design<DT, CPT, 8, CL>(a, plan, stream, err);
+    default: return launch_design<DT, CPT, 0, CL>(a, plan, stream, err);
+    }
+}
+
+template <int DT, int CPT>
+static int launch_design_c(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+{
+    return plan.coords_lds ? launch_design_p<DT, CPT, true>(a, plan, stream, err)
+                           : launch_design_p<DT, CPT, false>(a, plan, stream, err);
+}
+
+template <int DT>
+static int launch_design_dt(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+{
+    switch (plan.cpt) {
+    case 1: return launch_design_c<DT, 1>(a, plan, stream, err);
+    case 2: return launch_design_c<DT, 2>(a, plan, stream, err);
+    case 4: return launch_design_c<DT, 4>(a, plan, stream, err);
+    case 8: return launch_design_c<DT, 8>(a, plan, stream, err);
+    default: return launch_design_c<DT, 8>(a, plan, stream, err);
     }
 }
 
@@ -515,13 +714,8 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
         *err = "hipMemsetAsync failed";
         return -2;
     }
-    switch (plan.cpt) {
-    case 1: return launch_design_p<1>(a, plan, stream, err);
-    case 2: return launch_design_p<2>(a, plan, stream, err);
-    case 4: return launch_design_p<4>(a, plan, stream, err);
-    case 8: return launch_design_p<8>(a, plan, stream, err);
-    default: return launch_design_p<16>(a, plan, stream, err);
-    }
+    return plan.threads == 256 ? launch_design_dt<256>(a, plan, stream, err)
+                               : launch_design_dt<512>(a, plan, stream, err);
 }
 
 }  // namespace lagp

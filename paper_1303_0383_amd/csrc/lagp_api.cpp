@@ -4,6 +4,8 @@
 // locations.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -25,6 +27,8 @@ struct lagp_design {
     double* y = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // triples: before kNN, after kNN, after design
 };
 
 namespace {
@@ -164,6 +168,7 @@ void lagp_design_destroy(lagp_design* d)
 {
     if (!d) return;
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
     if (d->Xaos) (void)hipFree(d->Xaos);
     if (d->Xsoa) (void)hipFree(d->Xsoa);
     if (d->y) (void)hipFree(d->y);
@@ -201,6 +206,8 @@ static int plan_for(const lagp_design* d, int32_t nmax, int32_t Mmax, const lagp
                     lagp::DesignPlan* plan, size_t* knn_bytes, size_t* cand_bytes, size_t* design_bytes)
 {
     std::string err;
+    const char* thr = getenv("LAGP_DESIGN_THREADS");
+    plan->threads = (thr && atoi(thr) == 512) ? 512 : 256;
     if (lagp::design_plan(d->dev, nmax, Mmax, prm->n0, prm->precision, d->num_cu, d->max_lds, plan, &err))
         return fail(LAGP_E_INVAL, err);
     *knn_bytes = lagp::align256(lagp::knn_workspace_bytes(tc, kBucketMax));
@@ -277,6 +284,12 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     size_t kb, cb, db;
     rc = plan_for(d, nmax, Mmax, prm, tc_max, &plan, &kb, &cb, &db);
     if (rc) return rc;
+    if (getenv("LAGP_VERBOSE"))
+        fprintf(stderr,
+                "[lagp] plan: n=%d ncand=%d p=%d threads=%d slots/thread=%d rows: reg=%d lds=%d global=%d "
+                "coords_lds=%d lds=%zu B global_row_reads/loc=%lld workspace=%zu B\n",
+                nmax, Mmax, d->dev.p, plan.threads, plan.cpt, plan.rreg, plan.rlds, plan.rglob,
+                (int)plan.coords_lds, plan.lds_bytes, plan.global_row_reads, kb + cb + db);
     rc = ensure_ws(d, kb + cb + db, s);
     if (rc) return rc;
     char* base = (char*)d->ws;
@@ -287,9 +300,19 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
         const int64_t tc = std::min(kChunk, T - t0);
         std::string err;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (d->timing) {
+            for (int k = 0; k < 3; ++k) {
+                hipError_t e = hipEventCreate(&ev[k]);
+                if (e != hipSuccess) return hip_fail("hipEventCreate", e);
+                d->ev.push_back(ev[k]);
+            }
+            (void)hipEventRecord(ev[0], s);
+        }
         int r = lagp::knn_run(d->dev, XX + t0 * d->dev.p, tc, Mmax, ncand_per ? ncand_per + t0 : nullptr, cand,
                               Mmax, false, knn_ws, kb, s, d->num_cu, d->max_lds, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        if (d->timing) (void)hipEventRecord(ev[1], s);
         lagp::DesignLaunch L;
         L.XX = XX + t0 * d->dev.p;
         L.T = tc;
@@ -312,6 +335,7 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         L.status = status ? status + t0 : nullptr;
         r = lagp::design_run(d->dev, L, plan, des_ws, db, s, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        if (d->timing) (void)hipEventRecord(ev[2], s);
     }
     if (prm->flags & LAGP_STRICT) {
         if (!status) return fail(LAGP_E_INVAL, "strict mode needs the status output");
@@ -322,6 +346,37 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         for (int8_t v : hs)
             if (v != LAGP_LOC_OK) return fail(LAGP_E_NOTPD, "some location's local covariance was not positive definite");
     }
+    return LAGP_OK;
+}
+
+int lagp_timing_enable(lagp_design* d, int enable)
+{
+    if (!d) return fail(LAGP_E_INVAL, "design is NULL");
+    d->timing = enable != 0;
+    return LAGP_OK;
+}
+
+int lagp_phase_times(lagp_design* d, double* knn_ms, double* design_ms, int64_t* launches)
+{
+    if (!d) return fail(LAGP_E_INVAL, "design is NULL");
+    double a = 0.0, b = 0.0;
+    int64_t n = 0;
+    for (size_t k = 0; k + 2 < d->ev.size() + 0; k += 3) {
+        hipError_t e = hipEventSynchronize(d->ev[k + 2]);
+        if (e != hipSuccess) return hip_fail("hipEventSynchronize", e);
+        float x = 0.f, y = 0.f;
+        if (hipEventElapsedTime(&x, d->ev[k], d->ev[k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&y, d->ev[k + 1], d->ev[k + 2]) != hipSuccess)
+            return fail(LAGP_E_HIP, "hipEventElapsedTime failed");
+        a += x;
+        b += y;
+        ++n;
+    }
+    for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+    d->ev.clear();
+    if (knn_ms) *knn_ms = a;
+    if (design_ms) *design_ms = b;
+    if (launches) *launches = n;
     return LAGP_OK;
 }
 

@@ -66,6 +66,7 @@ struct DesignLaunch {
 };
 
 struct DesignPlan {
+    int threads = 0;       // workgroup size
     int cpt = 0;           // candidate slots per thread
     int rreg = 0;          // register-resident tile rows
     int rlds = 0;          // LDS-resident tile rows
@@ -75,6 +76,7 @@ struct DesignPlan {
     size_t lds_bytes = 0;
     size_t scratch_per_block = 0;  // bytes of global scratch per block
     size_t counter_bytes = 0;
+    long long global_row_reads = 0;  // modelled candidate-row reads from global memory per location
 };
 
 int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
