@@ -144,10 +144,11 @@ __host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl)
                      : (cpt >= 4 ? 0 : cpt == 2 ? 4 : 16);
 }
 
-// Rows per prefetch block of the global part of the tile.
+// Rows per prefetch block of the global part of the tile (two blocks are in
+// flight).
 __host__ __device__ constexpr int prefetch_rows(int cpt)
 {
-    return cpt >= 8 ? 1 : 8 / cpt;
+    return cpt >= 4 ? 2 : 8 / cpt;
 }
 
 // Combine (value, design index, slot) with a partner lane's triple.
@@ -316,6 +317,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
                             if (l < i) ws[l] = Wr[l][k];
                         misc[0] = v[k];
+                        ctl[1] = ci[k];
                     }
                 }
                 chosen |= 1u << kk;
@@ -384,7 +386,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 if (tid == 0) {
                     wx[i] = div_by(ax, delta, rdelta);
                     uu[i] = div_by(ay, delta, rdelta);
-                    if (A.sel) A.sel[t * A.sel_stride + i] = cand[s];
+                    if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
                 }
                 break;
             }
@@ -414,6 +416,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 // those terms subtract an exact 0.
                 const int le = i < G0 ? i : G0;
                 constexpr int QB = CPT >= 8 ? 1 : CPT == 4 ? 2 : 4;   // rows loaded ahead
+#pragma unroll 2
                 for (int l0 = RREG; l0 < le; l0 += 4) {
                     double w[4], xv[4], uv[4];
                     ld4(ws + l0, w);
@@ -476,7 +479,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (tid == 0) {
                 wx[i] = rx;
                 uu[i] = div_by(ay, delta, rdelta);
-                if (A.sel) A.sel[t * A.sel_stride + i] = cand[s];
+                if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
             }
             double r[CPT];
 #pragma unroll
