@@ -81,7 +81,18 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--cpu-sample", type=int, default=2048, help="locations in the CPU oracle sample (0: skip)")
     ap.add_argument("--parity-sample", type=int, default=64, help="sampled locations checked against the oracle")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8}))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
