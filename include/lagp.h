@@ -64,8 +64,10 @@ enum { LAGP_LOC_OK = 0, LAGP_LOC_NOTPD = 1 };
  * cov_j(x,c), the factor update and the final prediction are FP64 in every
  * mode. */
 typedef enum {
-    LAGP_PREC_FP64 = 0,        /* everything FP64                               */
-    LAGP_PREC_SCORE_FP32 = 1   /* whitened candidate tile stored and contracted in FP32 */
+    LAGP_PREC_FP64 = 0,        /* everything FP64; the prediction reuses the greedy factor */
+    LAGP_PREC_SCORE_FP32 = 1   /* ranking tile stored and contracted in FP32; K(s,c), v, cov,
+                                  the update and the argmax FP64; the prediction refactorises
+                                  K_n in FP64 from the chosen indices (n <= ~190) */
 } lagp_precision;
 
 /* Flags. */
@@ -119,6 +121,17 @@ int lagp_predict(const lagp_design *design, const double *XX, int64_t T, const l
                  const int32_t *n_per, const int32_t *ncand_per, double *mean, double *s2,
                  int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
                  void *stream);
+
+/* Local GP prediction from given local designs (eqs predgp, preds2 with
+ * N -> n): for each location t, K_n = K(D_t, D_t) + g I over the n (or n_per[t])
+ * design indices sel[t * sel_stride + 0 .. n-1] is factorised afresh in FP64
+ * and mean, s2, df, var written as in lagp_predict.  A location with an index
+ * outside [0, N) or a non-positive pivot gets status LAGP_LOC_NOTPD and NaN
+ * outputs.  Device pointers; n is limited by LDS (about 190 on gfx950). */
+int lagp_predict_designs(const lagp_design *design, const double *XX, int64_t T, const int32_t *sel,
+                         int64_t sel_stride, const int32_t *n_per, int32_t n, double d, double g,
+                         double *mean, double *s2, int32_t *df, double *var, int8_t *status,
+                         void *stream);
 
 /* Device bytes of workspace lagp_predict needs for a batch of T locations
  * with the given maxima (for admission control by callers). */

@@ -43,12 +43,14 @@ _lib.lagp_design_destroy.restype = None
 _lib.lagp_knn.argtypes = [_P, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]
 _lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P,
                               C.c_int64, _P, _P]
+_lib.lagp_predict_designs.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int32, C.c_double, C.c_double,
+                                      _P, _P, _P, _P, _P, _P]
 _lib.lagp_workspace_bytes.argtypes = [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
 _lib.lagp_timing_enable.argtypes = [_P, C.c_int]
 _lib.lagp_phase_times.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.lagp_last_error.restype = C.c_char_p
 for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
-           "lagp_version", "lagp_timing_enable", "lagp_phase_times"):
+           "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -129,6 +131,12 @@ def lagp_predict(design, XX, T: int, params: lagp_params, n_per, ncand_per, mean
                              _stream(stream)))
 
 
+def lagp_predict_designs(design, XX, T: int, sel, sel_stride: int, n_per, n: int, d: float, g: float, mean, s2,
+                         df, var, status, stream=None) -> None:
+    _check(_lib.lagp_predict_designs(design, _ptr(XX), T, _ptr(sel), sel_stride, _ptr(n_per), n, d, g, _ptr(mean),
+                                     _ptr(s2), _ptr(df), _ptr(var), _ptr(status), _stream(stream)))
+
+
 def lagp_workspace_bytes(design, T: int, nmax: int, ncand_max: int) -> int:
     out = C.c_size_t()
     _check(_lib.lagp_workspace_bytes(design, T, nmax, ncand_max, C.byref(out)))
@@ -185,6 +193,22 @@ class Design:
         idx = torch.empty((XX.shape[0], M), dtype=torch.int32, device=XX.device)
         lagp_knn(self._h, XX, XX.shape[0], M, idx, M, stream)
         return idx
+
+    def predict_designs(self, XX, sel, d: float, g: float, n_per=None, stream=None) -> Prediction:
+        """Prediction from given local designs (sel: T x n int32 design indices)."""
+        import torch
+        XX = XX.contiguous()
+        sel = sel.contiguous()
+        T, n = sel.shape
+        dev = XX.device
+        out = Prediction(mean=torch.empty(T, dtype=torch.float64, device=dev),
+                         s2=torch.empty(T, dtype=torch.float64, device=dev),
+                         df=torch.empty(T, dtype=torch.int32, device=dev),
+                         var=torch.empty(T, dtype=torch.float64, device=dev), sel=sel,
+                         status=torch.empty(T, dtype=torch.int8, device=dev))
+        lagp_predict_designs(self._h, XX, T, sel, n, n_per, n, d, g, out.mean, out.s2, out.df, out.var, out.status,
+                             stream)
+        return out
 
     def predict(self, XX, n0: int, n: int, ncand: int, d: float, g: float, n_per=None, ncand_per=None,
                 precision: int = LAGP_PREC_FP64, strict: bool = False, out: Optional[Prediction] = None,

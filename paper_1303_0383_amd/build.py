@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblagp.so")
-SOURCES = ["lagp_api.cpp", "knn.hip", "design.hip"]
+SOURCES = ["lagp_api.cpp", "knn.hip", "design.hip", "predict.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

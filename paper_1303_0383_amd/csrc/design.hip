@@ -138,10 +138,12 @@ __device__ __forceinline__ double sqdist_lds(const double* __restrict__ a, const
 // count.  With 256 threads (one wave per SIMD) a lane can hold 512 registers,
 // the upper half as accumulation registers the compiler uses as spill space;
 // with 512 threads a lane has 256.
-__host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl)
+__host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = false)
 {
-    return dt == 256 ? (cpt >= 16 ? 0 : cpt == 8 ? 4 : cpt == 4 ? (cl ? 16 : 12) : cpt == 2 ? 32 : 64)
-                     : (cpt >= 4 ? 0 : cpt == 2 ? 4 : 16);
+    return mix ? (dt == 256 ? (cpt >= 8 ? 8 : cpt == 4 ? (cl ? 24 : 16) : cpt == 2 ? 48 : 64)
+                            : (cpt >= 4 ? 0 : cpt == 2 ? 8 : 32))
+               : (dt == 256 ? (cpt >= 16 ? 0 : cpt == 8 ? 4 : cpt == 4 ? (cl ? 16 : 12) : cpt == 2 ? 32 : 64)
+                            : (cpt >= 4 ? 0 : cpt == 2 ? 4 : 16));
 }
 
 // Rows per prefetch block of the global part of the tile (two blocks are in
@@ -171,11 +173,20 @@ __device__ __forceinline__ void wave_pick(double& v, int& i, int& s)
     pick<MAX>(v, i, s, __shfl_xor(v, 32), __shfl_xor(i, 32), __shfl_xor(s, 32));
 }
 
+// Four consecutive LDS floats (16-byte aligned start).
+__device__ __forceinline__ void ld4(const float* p, float* o)
+{
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+}
+
 // DT threads per workgroup, CPT candidate slots per thread, RREG register
-// rows, P compile-time dimension (0: runtime), CL candidate coordinates in LDS.
-template <int DT, int CPT, int RREG, int P, bool CL>
+// rows, P compile-time dimension (0: runtime), CL candidate coordinates in LDS,
+// MIX: the whitened tile stored and contracted in FP32 (ranking only).
+template <int DT, int CPT, int RREG, int P, bool CL, bool MIX>
 __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 {
+    using TW = typename std::conditional<MIX, float, double>::type;
     constexpr int DWAVES = DT / 64;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
@@ -188,9 +199,9 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     const double rtheta = 1.0 / theta;
 
     // ---- LDS carve-up (doubles first, then ints)
-    double* ws = smem;               // [nmax] column of the chosen candidate
-    double* wx = ws + nmax;          // [nmax] L^{-1} k(x)
-    double* uu = wx + nmax;          // [nmax] L^{-1} Y
+    TW* ws = (TW*)smem;              // [nmax] column of the chosen candidate
+    TW* wx = (TW*)(smem + nmax);     // [nmax] L^{-1} k(x)
+    double* uu = smem + 2 * nmax;    // [nmax] L^{-1} Y
     double* xl = uu + nmax;          // [p]    predictive location
     double* xsl = xl + p;            // [p+1]  (spare)
     double* misc = xsl + p + 1;      // [4]    v_s
@@ -202,10 +213,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
     off = (off + 15) & ~(size_t)15;
     double* Xcl = (double*)((char*)smem + off);              // [p+1][Mpad] when CL: coordinates, y
-    double* Wl = Xcl + (CL ? (size_t)(p + 1) * Mpad : 0);     // [rlds][Mpad]
+    TW* Wl = (TW*)(Xcl + (CL ? (size_t)(p + 1) * Mpad : 0));  // [rlds][Mpad]
 
     double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-    double* Wg = Xcg + (CL ? 0 : (int64_t)(p + 1) * Mpad);
+    TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)(p + 1) * Mpad));
     double* Xc = CL ? Xcl : Xcg;
     const int rlds = A.rlds;
     const int G0 = RREG + rlds;   // first global row
@@ -238,7 +249,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         //      K(x,c) and v_0(c) = 1 + g
         int ci[CPT];
         double v[CPT], cov[CPT], d2[CPT];
-        double Wr[RREG > 0 ? RREG : 1][CPT];
+        TW Wr[RREG > 0 ? RREG : 1][CPT];
 #pragma unroll
         for (int l = 0; l < (RREG > 0 ? RREG : 1); ++l)
 #pragma unroll
@@ -359,13 +370,16 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 
             // Prefetch the first global rows.
             constexpr int U = prefetch_rows(CPT);
-            double pre[U][CPT];
+            TW pre[U][CPT];
+            float dot[CPT], dotx = 0.0f;   // FP32 contraction (MIX)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) dot[k] = 0.0f;
             const int gcount = i > G0 ? i - G0 : 0;
             if (gcount > 0) {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (u < gcount) {
-                        const double* row = Wg + (int64_t)u * Mpad + tid;
+                        const TW* row = Wg + (int64_t)u * Mpad + tid;
 #pragma unroll
                         for (int k = 0; k < CPT; ++k) pre[u][k] = row[k * DT];
                     }
@@ -380,7 +394,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (i == n - 1) {
                 for (int l = 0; l < i; ++l) {
                     const double w = ws[l];
-                    ax -= w * wx[l];
+                    ax -= w * (double)wx[l];
                     ay -= w * uu[l];
                 }
                 if (tid == 0) {
@@ -396,16 +410,26 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
             for (int l0 = 0; l0 < (RREG > 0 ? RREG : 0); l0 += 4) {
                 if (l0 < i) {
-                    double w[4], xv[4], uv[4];
+                    TW w[4], xv[4];
                     ld4(ws + l0, w);
                     ld4(wx + l0, xv);
-                    ld4(uu + l0, uv);
+                    if constexpr (MIX) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                        for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                        for (int k = 0; k < CPT; ++k) acc[k] -= w[r] * Wr[l0 + r][k];
-                        ax -= w[r] * xv[r];
-                        ay -= w[r] * uv[r];
+                            for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(w[r], Wr[l0 + r][k], dot[k]);
+                            dotx = __builtin_fmaf(w[r], xv[r], dotx);
+                        }
+                    } else {
+                        double uv[4];
+                        ld4(uu + l0, uv);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                            for (int k = 0; k < CPT; ++k) acc[k] -= w[r] * Wr[l0 + r][k];
+                            ax -= w[r] * xv[r];
+                            ay -= w[r] * uv[r];
+                        }
                     }
                 }
             }
@@ -418,27 +442,34 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 constexpr int QB = CPT >= 8 ? 1 : CPT == 4 ? 2 : 4;   // rows loaded ahead
 #pragma unroll 2
                 for (int l0 = RREG; l0 < le; l0 += 4) {
-                    double w[4], xv[4], uv[4];
+                    TW w[4], xv[4];
+                    double uv[4];
                     ld4(ws + l0, w);
                     ld4(wx + l0, xv);
-                    ld4(uu + l0, uv);
+                    if constexpr (!MIX) ld4(uu + l0, uv);
 #pragma unroll
                     for (int r0 = 0; r0 < 4; r0 += QB) {
-                        double q[QB][CPT];
+                        TW q[QB][CPT];
 #pragma unroll
                         for (int r = 0; r < QB; ++r) {
                             const int lr = (l0 + r0 + r < G0) ? l0 + r0 + r : l0;   // stay inside the LDS tile
-                            const double* row = Wl + (int64_t)(lr - RREG) * Mpad + tid;
+                            const TW* row = Wl + (int64_t)(lr - RREG) * Mpad + tid;
 #pragma unroll
                             for (int k = 0; k < CPT; ++k) q[r][k] = row[k * DT];
                         }
 #pragma unroll
                         for (int r = 0; r < QB; ++r) {
-                            const double wr = (l0 + r0 + r < le) ? w[r0 + r] : 0.0;
+                            const TW wr = (l0 + r0 + r < le) ? w[r0 + r] : (TW)0;
+                            if constexpr (MIX) {
 #pragma unroll
-                            for (int k = 0; k < CPT; ++k) acc[k] -= wr * q[r][k];
-                            ax -= wr * xv[r0 + r];
-                            ay -= wr * uv[r0 + r];
+                                for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wr, q[r][k], dot[k]);
+                                dotx = __builtin_fmaf(wr, xv[r0 + r], dotx);
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < CPT; ++k) acc[k] -= wr * q[r][k];
+                                ax -= wr * xv[r0 + r];
+                                ay -= wr * uv[r0 + r];
+                            }
                         }
                     }
                 }
@@ -451,22 +482,28 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     const int nb = (i - l) < U ? (i - l) : U;     // rows in pre[]
                     const int l2 = l + nb;
                     const int nb2 = (i - l2) < U ? (i - l2) : U;   // rows of the next block
-                    double nxt[U][CPT];
+                    TW nxt[U][CPT];
 #pragma unroll
                     for (int u = 0; u < U; ++u)
                         if (u < nb2) {
-                            const double* row = Wg + (int64_t)(l2 + u - G0) * Mpad + tid;
+                            const TW* row = Wg + (int64_t)(l2 + u - G0) * Mpad + tid;
 #pragma unroll
                             for (int k = 0; k < CPT; ++k) nxt[u][k] = row[k * DT];
                         }
 #pragma unroll
                     for (int u = 0; u < U; ++u)
                         if (u < nb) {
-                            const double w = ws[l + u];
+                            const TW w = ws[l + u];
+                            if constexpr (MIX) {
 #pragma unroll
-                            for (int k = 0; k < CPT; ++k) acc[k] -= w * pre[u][k];
-                            ax -= w * wx[l + u];
-                            ay -= w * uu[l + u];
+                                for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(w, pre[u][k], dot[k]);
+                                dotx = __builtin_fmaf(w, wx[l + u], dotx);
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < CPT; ++k) acc[k] -= w * pre[u][k];
+                                ax -= w * wx[l + u];
+                                ay -= w * uu[l + u];
+                            }
                         }
 #pragma unroll
                     for (int u = 0; u < U; ++u)
@@ -475,7 +512,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     l = l2;
                 }
             }
-            const double rx = div_by(ax, delta, rdelta);
+            if constexpr (MIX) {
+                ax -= (double)dotx;
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) acc[k] -= (double)dot[k];
+            }
+            const double rx = MIX ? ax * rdelta : div_by(ax, delta, rdelta);
             if (tid == 0) {
                 wx[i] = rx;
                 uu[i] = div_by(ay, delta, rdelta);
@@ -484,7 +526,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             double r[CPT];
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
-                r[k] = div_by(acc[k], delta, rdelta);
+                r[k] = MIX ? acc[k] * rdelta : div_by(acc[k], delta, rdelta);
                 v[k] -= r[k] * r[k];
                 cov[k] -= rx * r[k];
             }
@@ -493,16 +535,16 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
                     if (l == i) {
 #pragma unroll
-                        for (int k = 0; k < CPT; ++k) Wr[l][k] = r[k];
+                        for (int k = 0; k < CPT; ++k) Wr[l][k] = (TW)r[k];
                     }
             } else if (i < G0) {
-                double* row = Wl + (int64_t)(i - RREG) * Mpad + tid;
+                TW* row = Wl + (int64_t)(i - RREG) * Mpad + tid;
 #pragma unroll
-                for (int k = 0; k < CPT; ++k) row[k * DT] = r[k];
+                for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
             } else {
-                double* row = Wg + (int64_t)(i - G0) * Mpad + tid;
+                TW* row = Wg + (int64_t)(i - G0) * Mpad + tid;
 #pragma unroll
-                for (int k = 0; k < CPT; ++k) row[k * DT] = r[k];
+                for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
             }
 
             // Argmax of ALC_{i+1} over live candidates (needed from step n0 on).
@@ -535,9 +577,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             }
         }
 
-        // ---- prediction (eqs predgp, preds2 with N -> n)
+        // ---- prediction (eqs predgp, preds2 with N -> n); with an FP32 tile the
+        //      prediction kernel refactorises K_n in FP64 from the indices.
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && !MIX) {
             double mean, s2v, var;
             if (notpd) {
                 mean = s2v = var = NAN;
@@ -587,7 +630,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, i
                 int num_cu, size_t max_lds, DesignPlan* plan, std::string* err)
 {
     (void)n0;
-    (void)precision;
+    const bool mix = precision != 0;
     int dt = plan->threads == 512 ? 512 : 256;
     if (Mmax > 2048) dt = 512;   // at most 8 slots per thread
     int cpt = 1;
@@ -598,35 +641,35 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, i
     const int rows = nmax > 1 ? nmax - 1 : 0;  // W rows ever stored
     const size_t fixed = fixed_lds_bytes(nmax, p, dt);
     if (fixed > max_lds) { *err = "local design size too large for LDS"; return -1; }
-    const size_t row_bytes = (size_t)Mpad * sizeof(double);
-    const int cap = (int)((max_lds - fixed) / row_bytes);   // LDS rows available
+    const size_t row_bytes = (size_t)Mpad * (mix ? sizeof(float) : sizeof(double));   // tile row
+    const size_t crow_bytes = (size_t)Mpad * sizeof(double);                          // coordinate row
+    const size_t avail = max_lds - fixed;
     // Option A: coordinates in LDS.  Option B: coordinates in global memory.
+    // Cost: bytes read from global memory per location.
     const int pc = p + 1;   // coordinate rows plus the response
-    const int rregA = rreg_for(dt, cpt, true), rregB = rreg_for(dt, cpt, false);
+    const int rregA = rreg_for(dt, cpt, true, mix), rregB = rreg_for(dt, cpt, false, mix);
     const int remA = rows > rregA ? rows - rregA : 0, remB = rows > rregB ? rows - rregB : 0;
     long long costA = -1, costB;
     int rldsA = 0;
-    if (cap >= pc) {
-        rldsA = std::min(remA, cap - pc);
-        costA = global_row_reads(nmax, rregA + rldsA);
+    if (avail >= pc * crow_bytes) {
+        rldsA = std::min<long long>(remA, (avail - pc * crow_bytes) / row_bytes);
+        costA = global_row_reads(nmax, rregA + rldsA) * (long long)row_bytes;
     }
-    const int rldsB = std::min(remB, cap);
-    costB = (long long)pc * (nmax - 1) + global_row_reads(nmax, rregB + rldsB);
+    const int rldsB = std::min<long long>(remB, avail / row_bytes);
+    costB = (long long)pc * (nmax - 1) * (long long)crow_bytes + global_row_reads(nmax, rregB + rldsB) * (long long)row_bytes;
     const bool cl = costA >= 0 && costA <= costB;
-    const int rlds = cl ? rldsA : rldsB;
-    const int rreg = cl ? rregA : rregB;
-    const int rem = cl ? remA : remB;
     plan->cpt = cpt;
     plan->threads = dt;
-    plan->rreg = rreg;
-    plan->rlds = rlds;
-    plan->rglob = rem - rlds;
+    plan->mix = mix;
+    plan->rreg = cl ? rregA : rregB;
+    plan->rlds = cl ? rldsA : rldsB;
+    plan->rglob = (cl ? remA : remB) - plan->rlds;
     plan->coords_lds = cl;
-    plan->lds_bytes = fixed + (cl ? (size_t)pc * row_bytes : 0) + (size_t)rlds * row_bytes;
-    plan->scratch_per_block = align256(((cl ? 0 : (size_t)pc) + (size_t)plan->rglob) * row_bytes);
+    plan->lds_bytes = fixed + (cl ? pc * crow_bytes : 0) + (size_t)plan->rlds * row_bytes;
+    plan->scratch_per_block = align256((cl ? 0 : pc * crow_bytes) + (size_t)plan->rglob * row_bytes);
     plan->blocks = num_cu;
     plan->counter_bytes = 256;
-    plan->global_row_reads = cl ? costA : costB;
+    plan->global_row_reads = (cl ? costA : costB) / (long long)row_bytes;
     return 0;
 }
 
@@ -635,11 +678,11 @@ size_t design_workspace_bytes(const DesignPlan& plan)
     return plan.counter_bytes + plan.scratch_per_block * (size_t)plan.blocks;
 }
 
-template <int DT, int CPT, int P, bool CL>
+template <int DT, int CPT, int P, bool CL, bool MIX>
 static int launch_design(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    constexpr int RREG = rreg_for(DT, CPT, CL);
-    auto kern = design_kernel<DT, CPT, RREG, P, CL>;
+    constexpr int RREG = rreg_for(DT, CPT, CL, MIX);
+    auto kern = design_kernel<DT, CPT, RREG, P, CL, MIX>;
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)plan.lds_bytes) != hipSuccess) {
         *err = "cannot reserve LDS for the design kernel";
@@ -650,22 +693,25 @@ static int launch_design(const DesignArgs& a, const DesignPlan& plan, hipStream_
     return 0;
 }
 
-template <int DT, int CPT, bool CL>
+template <int DT, int CPT, bool CL, bool MIX>
 static int launch_design_p(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     switch (a.p) {
-    case 2: return launch_design<DT, CPT, 2, CL>(a, plan, stream, err);
-    case 4: return launch_design<DT, CPT, 4, CL>(a, plan, stream, err);
-    case 8: return launch_design<DT, CPT, 8, CL>(a, plan, stream, err);
-    default: return launch_design<DT, CPT, 0, CL>(a, plan, stream, err);
+    case 2: return launch_design<DT, CPT, 2, CL, MIX>(a, plan, stream, err);
+    case 4: return launch_design<DT, CPT, 4, CL, MIX>(a, plan, stream, err);
+    case 8: return launch_design<DT, CPT, 8, CL, MIX>(a, plan, stream, err);
+    default: return launch_design<DT, CPT, 0, CL, MIX>(a, plan, stream, err);
     }
 }
 
 template <int DT, int CPT>
 static int launch_design_c(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    return plan.coords_lds ? launch_design_p<DT, CPT, true>(a, plan, stream, err)
-                           : launch_design_p<DT, CPT, false>(a, plan, stream, err);
+    if (plan.mix)
+        return plan.coords_lds ? launch_design_p<DT, CPT, true, true>(a, plan, stream, err)
+                               : launch_design_p<DT, CPT, false, true>(a, plan, stream, err);
+    return plan.coords_lds ? launch_design_p<DT, CPT, true, false>(a, plan, stream, err)
+                           : launch_design_p<DT, CPT, false, false>(a, plan, stream, err);
 }
 
 template <int DT>

@@ -67,6 +67,44 @@ __global__ void aos_to_soa_kernel(const double* __restrict__ aos, double* __rest
     soa[(int64_t)k * N + i] = aos[e];
 }
 
+// Rows idx[0..m-1] of src (row length w) into dst (m x w).
+template <typename T>
+__global__ void gather_rows_kernel(const T* __restrict__ src, int64_t w, const int64_t* __restrict__ idx, int64_t m,
+                                   T* __restrict__ dst)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * w) return;
+    int64_t r = e / w, c = e - r * w;
+    dst[e] = src[idx[r] * w + c];
+}
+
+// Rows of src (m x w) back to rows idx[r] of dst (row stride dstride >= w).
+template <typename T>
+__global__ void scatter_rows_kernel(const T* __restrict__ src, int64_t w, const int64_t* __restrict__ idx, int64_t m,
+                                    T* __restrict__ dst, int64_t dstride)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * w) return;
+    int64_t r = e / w, c = e - r * w;
+    dst[idx[r] * dstride + c] = src[e];
+}
+
+template <typename T>
+void gather_rows(const T* src, int64_t w, const int64_t* idx, int64_t m, T* dst, hipStream_t s)
+{
+    if (m * w == 0) return;
+    hipLaunchKernelGGL(gather_rows_kernel<T>, dim3((unsigned)((m * w + 255) / 256)), dim3(256), 0, s, src, w, idx, m,
+                       dst);
+}
+
+template <typename T>
+void scatter_rows(const T* src, int64_t w, const int64_t* idx, int64_t m, T* dst, int64_t dstride, hipStream_t s)
+{
+    if (m * w == 0 || !dst) return;
+    hipLaunchKernelGGL(scatter_rows_kernel<T>, dim3((unsigned)((m * w + 255) / 256)), dim3(256), 0, s, src, w, idx,
+                       m, dst, dstride);
+}
+
 int ensure_ws(lagp_design* d, size_t bytes, hipStream_t stream)
 {
     if (bytes <= d->ws_bytes) return LAGP_OK;
@@ -231,6 +269,65 @@ int lagp_workspace_bytes(const lagp_design* design, int64_t T, int32_t nmax, int
 
 int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
                  const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
+                 int32_t* sel, int64_t sel_stride, int8_t* status, void* stream);
+
+// Re-run the locations `idx` in FP64 and scatter their outputs back.
+static int redo_fp64(lagp_design* d, const double* XX, const lagp_params* prm, const int32_t* n_per,
+                     const int32_t* ncand_per, const std::vector<int64_t>& idx, int32_t nmax, double* mean, double* s2,
+                     int32_t* df, double* var, int32_t* sel, int64_t sel_stride, int8_t* status, hipStream_t s)
+{
+    const int64_t m = (int64_t)idx.size();
+    const int p = d->dev.p;
+    size_t bytes = lagp::align256(m * sizeof(int64_t)) + lagp::align256(m * p * sizeof(double)) +
+                   2 * lagp::align256(m * sizeof(int32_t)) + 3 * lagp::align256(m * sizeof(double)) +
+                   lagp::align256(m * sizeof(int32_t)) + lagp::align256(m * nmax * sizeof(int32_t)) +
+                   lagp::align256(m);
+    char* buf = nullptr;
+    hipError_t e = hipMalloc(&buf, bytes);
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(LAGP_E_NOMEM, "FP64 redo buffer allocation failed"); }
+    char* q = buf;
+    auto take = [&](size_t b) { char* r = q; q += lagp::align256(b); return r; };
+    int64_t* di = (int64_t*)take(m * sizeof(int64_t));
+    double* xx = (double*)take(m * p * sizeof(double));
+    int32_t* np_ = (int32_t*)take(m * sizeof(int32_t));
+    int32_t* mp_ = (int32_t*)take(m * sizeof(int32_t));
+    double* me = (double*)take(m * sizeof(double));
+    double* sc = (double*)take(m * sizeof(double));
+    double* va = (double*)take(m * sizeof(double));
+    int32_t* dfo = (int32_t*)take(m * sizeof(int32_t));
+    int32_t* so = (int32_t*)take(m * nmax * sizeof(int32_t));
+    int8_t* sto = (int8_t*)take(m);
+    int rc = LAGP_OK;
+    e = hipMemcpyAsync(di, idx.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { rc = hip_fail("redo index copy", e); goto done; }
+    gather_rows<double>(XX, p, di, m, xx, s);
+    if (n_per) gather_rows<int32_t>(n_per, 1, di, m, np_, s);
+    if (ncand_per) gather_rows<int32_t>(ncand_per, 1, di, m, mp_, s);
+    {
+        lagp_params q64 = *prm;
+        q64.precision = LAGP_PREC_FP64;
+        q64.flags = 0;
+        rc = lagp_predict(d, xx, m, &q64, n_per ? np_ : nullptr, ncand_per ? mp_ : nullptr, me, sc, dfo, va, so, nmax,
+                          sto, s);
+    }
+    if (rc) goto done;
+    scatter_rows<double>(me, 1, di, m, mean, 1, s);
+    scatter_rows<double>(sc, 1, di, m, s2, 1, s);
+    scatter_rows<double>(va, 1, di, m, var, 1, s);
+    scatter_rows<int32_t>(dfo, 1, di, m, df, 1, s);
+    scatter_rows<int8_t>(sto, 1, di, m, status, 1, s);
+    scatter_rows<int32_t>(so, nmax, di, m, sel, sel_stride, s);
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail("FP64 redo", e);
+done:
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    return rc;
+}
+
+int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                 const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
                  int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
 {
     if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
@@ -238,7 +335,8 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     const int64_t N = design->dev.N;
     if (!(prm->d > 0.0) || !isfinite(prm->d)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
     if (!(prm->g >= 0.0) || !isfinite(prm->g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
-    if (prm->precision != LAGP_PREC_FP64) return fail(LAGP_E_INVAL, "unsupported precision mode");
+    if (prm->precision != LAGP_PREC_FP64 && prm->precision != LAGP_PREC_SCORE_FP32)
+        return fail(LAGP_E_INVAL, "unsupported precision mode");
     if (prm->flags & ~(uint32_t)LAGP_STRICT) return fail(LAGP_E_INVAL, "unknown flag");
     if (prm->n0 < 1) return fail(LAGP_E_INVAL, "n0 must be >= 1");
     if (!n_per && (prm->n < prm->n0)) return fail(LAGP_E_INVAL, "n must be >= n0");
@@ -284,18 +382,27 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     size_t kb, cb, db;
     rc = plan_for(d, nmax, Mmax, prm, tc_max, &plan, &kb, &cb, &db);
     if (rc) return rc;
+    const bool mix = prm->precision == LAGP_PREC_SCORE_FP32;
+    if (mix && lagp::predict_lds_bytes(nmax) > d->max_lds)
+        return fail(LAGP_E_INVAL, "n too large for the FP64 prediction kernel of the mixed mode");
+    // The mixed mode needs the selections for its FP64 prediction pass.
+    const size_t sb = (mix && !sel) ? lagp::align256((size_t)tc_max * nmax * sizeof(int32_t)) : 0;
+    // ... and the per-location status to find locations to redo in FP64.
+    const size_t stb = (mix && !status) ? lagp::align256((size_t)T) : 0;
     if (getenv("LAGP_VERBOSE"))
         fprintf(stderr,
                 "[lagp] plan: n=%d ncand=%d p=%d threads=%d slots/thread=%d rows: reg=%d lds=%d global=%d "
                 "coords_lds=%d lds=%zu B global_row_reads/loc=%lld workspace=%zu B\n",
                 nmax, Mmax, d->dev.p, plan.threads, plan.cpt, plan.rreg, plan.rlds, plan.rglob,
-                (int)plan.coords_lds, plan.lds_bytes, plan.global_row_reads, kb + cb + db);
-    rc = ensure_ws(d, kb + cb + db, s);
+                (int)plan.coords_lds, plan.lds_bytes, plan.global_row_reads, kb + cb + db + sb);
+    rc = ensure_ws(d, kb + cb + db + sb + stb, s);
     if (rc) return rc;
     char* base = (char*)d->ws;
     void* knn_ws = base;
     int32_t* cand = (int32_t*)(base + kb);
     void* des_ws = base + kb + cb;
+    int32_t* sel_ws = sb ? (int32_t*)(base + kb + cb + db) : nullptr;
+    int8_t* st_all = status ? status : (stb ? (int8_t*)(base + kb + cb + db + sb) : nullptr);
 
     for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
         const int64_t tc = std::min(kChunk, T - t0);
@@ -330,12 +437,32 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         L.s2 = s2 + t0;
         L.df = df ? df + t0 : nullptr;
         L.var = var ? var + t0 : nullptr;
-        L.sel = sel ? sel + t0 * sel_stride : nullptr;
-        L.sel_stride = sel_stride;
-        L.status = status ? status + t0 : nullptr;
+        L.sel = sel ? sel + t0 * sel_stride : sel_ws;
+        L.sel_stride = sel ? sel_stride : nmax;
+        L.status = st_all ? st_all + t0 : nullptr;
         r = lagp::design_run(d->dev, L, plan, des_ws, db, s, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        if (mix) {
+            r = lagp::predict_run(d->dev, L.XX, tc, L.sel, L.sel_stride, L.n_per, nmax, prm->d, prm->g, L.mean, L.s2,
+                                  L.df, L.var, L.status, d->max_lds, s, &err);
+            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        }
         if (d->timing) (void)hipEventRecord(ev[2], s);
+    }
+    if (mix) {
+        // FP32 ranking can lose positive definiteness where FP64 keeps it (tiny
+        // nuggets, near-duplicate neighbours): redo those locations in FP64.
+        std::vector<int8_t> hs(T);
+        hipError_t e = hipMemcpyAsync(hs.data(), st_all, T, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail("status copy", e);
+        std::vector<int64_t> redo;
+        for (int64_t t = 0; t < T; ++t)
+            if (hs[t] != LAGP_LOC_OK) redo.push_back(t);
+        if (!redo.empty()) {
+            rc = redo_fp64(d, XX, prm, n_per, ncand_per, redo, nmax, mean, s2, df, var, sel, sel_stride, status, s);
+            if (rc) return rc;
+        }
     }
     if (prm->flags & LAGP_STRICT) {
         if (!status) return fail(LAGP_E_INVAL, "strict mode needs the status output");
@@ -346,6 +473,43 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         for (int8_t v : hs)
             if (v != LAGP_LOC_OK) return fail(LAGP_E_NOTPD, "some location's local covariance was not positive definite");
     }
+    return LAGP_OK;
+}
+
+int lagp_predict_designs(const lagp_design* design, const double* XX, int64_t T, const int32_t* sel,
+                         int64_t sel_stride, const int32_t* n_per, int32_t n, double dlen, double g, double* mean,
+                         double* s2, int32_t* df, double* var, int8_t* status, void* stream)
+{
+    if (!design) return fail(LAGP_E_INVAL, "design is NULL");
+    if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
+    if (!(dlen > 0.0) || !isfinite(dlen)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
+    if (!(g >= 0.0) || !isfinite(g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
+    if (T == 0) return LAGP_OK;
+    if (!XX || !sel || !mean || !s2) return fail(LAGP_E_INVAL, "XX, sel, mean and s2 are required");
+    const void* devptrs[] = {XX, sel, mean, s2, df, var, status, n_per};
+    for (const void* q : devptrs)
+        if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
+    int rc = check_device(design);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t nmax = n;
+    if (n_per) {
+        std::vector<int32_t> hn(T);
+        hipError_t e = hipMemcpyAsync(hn.data(), n_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail("per-location size copy", e);
+        nmax = 0;
+        for (int64_t t = 0; t < T; ++t) {
+            if (hn[t] < 1) return fail(LAGP_E_INVAL, "every n must be >= 1");
+            nmax = std::max(nmax, hn[t]);
+        }
+    }
+    if (nmax < 1) return fail(LAGP_E_INVAL, "n must be >= 1");
+    if (sel_stride < nmax) return fail(LAGP_E_INVAL, "sel_stride must be >= n");
+    std::string err;
+    int r = lagp::predict_run(design->dev, XX, T, sel, sel_stride, n_per, nmax, dlen, g, mean, s2, df, var, status,
+                              design->max_lds, s, &err);
+    if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     return LAGP_OK;
 }
 

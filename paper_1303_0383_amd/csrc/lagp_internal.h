@@ -77,6 +77,7 @@ struct DesignPlan {
     size_t scratch_per_block = 0;  // bytes of global scratch per block
     size_t counter_bytes = 0;
     long long global_row_reads = 0;  // modelled candidate-row reads from global memory per location
+    bool mix = false;                // FP32 tile
 };
 
 int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
@@ -84,5 +85,11 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, i
 size_t design_workspace_bytes(const DesignPlan& plan);
 int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& plan, void* ws,
                size_t ws_bytes, hipStream_t stream, std::string* err);
+
+// ---- prediction from given local designs (predict.hip)
+size_t predict_lds_bytes(int nmax);
+int predict_run(const DeviceDesign& D, const double* XX, int64_t T, const int32_t* sel, int64_t sel_stride,
+                const int32_t* n_per, int32_t nmax, double theta, double eta, double* mean, double* s2,
+                int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream, std::string* err);
 
 }  // namespace lagp

@@ -81,3 +81,42 @@ def compare(X, y, XX, n0, n, M, d, g, res, idx=None, n_per=None, M_per=None):
             assert ev <= VAR_TOL, f"location {t}: var rel err {ev:.3e}"
     worst.update(identical=identical, replayed=replayed)
     return worst
+
+
+def mixed_metrics(X, y, XX, n0, n, M, d, g, res, idx=None):
+    """Mixed-precision quality against the FP64 oracle.
+
+    * step agreement: the oracle replays the GPU's choices; a greedy step
+      agrees when the GPU's choice is the oracle's argmax within a relative
+      gap of 1e-8 (counted over all greedy steps of all locations);
+    * sequence agreement: fraction of locations whose whole sequence equals
+      the oracle's own;
+    * mean RMS difference from the oracle's own prediction, over sd(y);
+    * prediction parity: the GPU's FP64 prediction from its own selections
+      against the oracle's prediction from the same selections."""
+    T = XX.shape[0]
+    idx = list(range(T)) if idx is None else list(idx)
+    steps = agree = same_seq = 0
+    dmu = []
+    worst_pred = 0.0
+    sdy = float(np.std(y))
+    notpd = 0
+    for t in idx:
+        rc, s_o, o, _ = oracle.local(X, y, XX[t], n0, n, M, d, g)
+        if res["status"][t] != 0:
+            assert rc == oracle.NOTPD, f"location {t}: GPU NOTPD where the FP64 oracle succeeds"
+            notpd += 1
+            continue
+        s_g = res["sel"][t, :n]
+        rc2, _, o_r, diag = oracle.local(X, y, XX[t], n0, n, M, d, g, replay=s_g)
+        a1, ach = diag[n0:, 0], diag[n0:, 2]
+        ok = (a1 - ach) <= GAP_TOL * np.where(a1 > 0, a1, 1.0)
+        steps += len(ok)
+        agree += int(ok.sum())
+        same_seq += int(np.array_equal(s_g, s_o))
+        dmu.append(res["mean"][t] - o[0])
+        worst_pred = max(worst_pred, abs(res["mean"][t] - o_r[0]) / max(abs(o_r[0]), sdy),
+                         abs(res["s2"][t] - o_r[1]) / o_r[1])
+    return {"step_agreement": agree / max(steps, 1), "sequence_agreement": same_seq / max(len(idx), 1),
+            "mean_rms_over_sd": float(np.sqrt(np.mean(np.square(dmu)))) / sdy, "prediction_parity": worst_pred,
+            "notpd": notpd}

@@ -227,3 +227,59 @@ def test_invalid_arguments(c0, lagp):
         assert e.value.code == lagp.LAGP_E_INVAL
     with pytest.raises(lagp.LagpError):
         D.predict(torch.as_tensor(w.XX[:4]), 2, 10, 20, 0.5, 1e-6)   # host tensor
+
+
+# --------------------------------------------------- prediction from designs
+def test_predict_designs_matches_oracle(c2, lagp):
+    import torch
+    w, D = c2
+    XX = w.XX[500:540]
+    sel = np.stack([oracle.local(w.X, w.y, XX[t], w.n0, 50, w.ncand, w.d, w.g)[1] for t in range(len(XX))])
+    out = D.predict_designs(torch.as_tensor(XX, device="cuda:0"), torch.as_tensor(sel, device="cuda:0"), w.d, w.g)
+    torch.cuda.synchronize()
+    for t in range(len(XX)):
+        rc, ref = oracle.predict(w.X, w.y, XX[t], sel[t], w.d, w.g)
+        assert abs(out.mean[t].item() - ref[0]) <= 1e-9 * max(abs(ref[0]), np.std(w.y))
+        assert abs(out.s2[t].item() - ref[1]) <= 1e-9 * ref[1]
+        assert abs(out.var[t].item() - ref[2]) <= 1e-9 * ref[2]
+        assert out.df[t].item() == 50 and out.status[t].item() == 0
+
+
+def test_predict_designs_rejects_bad_indices(c0, lagp):
+    import torch
+    w, D = c0
+    sel = torch.tensor([[0, 1, 2, 3], [0, 1, -1, 3], [0, 1, 2, 5000]], dtype=torch.int32, device="cuda:0")
+    out = D.predict_designs(torch.as_tensor(w.XX[:3], device="cuda:0"), sel, w.d, w.g)
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    assert st[0] == 0 and st[1] == 1 and st[2] == 1
+    assert np.isnan(out.mean[1].item()) and np.isnan(out.mean[2].item())
+
+
+# ------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("n", [50, 64])
+def test_mixed_precision_c2(c2, lagp, n):
+    w, D = c2
+    XX = w.XX[2000:2200]
+    res = gpu_predict(D, XX, w.n0, n, w.ncand, w.d, w.g, precision=lagp.LAGP_PREC_SCORE_FP32)
+    assert np.all(res["status"] == 0)
+    from parity import mixed_metrics
+    m = mixed_metrics(w.X, w.y, XX, w.n0, n, w.ncand, w.d, w.g, res, idx=range(0, 200, 4))
+    print("mixed c2 n=%d" % n, m)
+    assert m["step_agreement"] >= 0.99
+    assert m["prediction_parity"] <= 1e-9
+    # The mean RMS against the FP64 oracle is reported: locations whose greedy
+    # sequence takes a different near-tied step have a different (equally
+    # valid) local design, and their prediction moves by the local model error.
+    assert m["mean_rms_over_sd"] <= 1e-2
+
+
+def test_mixed_precision_c1_reported(c1, lagp):
+    # The 2-D workload has nugget 1e-6; FP32 ranking there is reported, not gated.
+    w, D = c1
+    XX = w.XX[::211]
+    res = gpu_predict(D, XX, w.n0, w.n, w.ncand, w.d, w.g, precision=lagp.LAGP_PREC_SCORE_FP32)
+    from parity import mixed_metrics
+    m = mixed_metrics(w.X, w.y, XX, w.n0, w.n, w.ncand, w.d, w.g, res, idx=range(0, len(XX), 2))
+    print("mixed c1", m)
+    assert m["prediction_parity"] <= 1e-9
