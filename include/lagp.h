@@ -67,7 +67,9 @@ typedef enum {
     LAGP_PREC_FP64 = 0,        /* everything FP64; the prediction reuses the greedy factor */
     LAGP_PREC_SCORE_FP32 = 1   /* ranking tile stored and contracted in FP32; K(s,c), v, cov,
                                   the update and the argmax FP64; the prediction refactorises
-                                  K_n in FP64 from the chosen indices (n <= ~190) */
+                                  K_n in FP64 from the chosen indices (n <= ~190); a location
+                                  whose FP32 ranking loses positive definiteness is redone
+                                  entirely in FP64 on the device */
 } lagp_precision;
 
 /* Flags. */
@@ -133,16 +135,67 @@ int lagp_predict_designs(const lagp_design *design, const double *XX, int64_t T,
                          double *mean, double *s2, int32_t *df, double *var, int8_t *status,
                          void *stream);
 
+/* ---- Fixed-shape batches (uneven sizes, HIP-graph replay).
+ *
+ * A batch fixes T and the per-location sizes once.  lagp_batch_create checks
+ * them (as lagp_predict does), groups the locations into buckets of similar
+ * (n, N') -- candidate-set size rounded up to a power of two >= 256 and
+ * design size to a power of two >= 32 -- orders each bucket by decreasing
+ * modelled cost n^2 N' (longest first, so that the persistent workgroups of
+ * a launch finish together), chooses each bucket's kernel variant (the tuned
+ * table shipped with the library, else the traffic model), and allocates all
+ * device memory the batch will use.  The work is that of lagp_predict on
+ * every location (Sections 3-4.1); results are identical to lagp_predict's.
+ *
+ *   n_per, ncand_per  HOST int32[T] arrays (nullable: params->n / ->ncand),
+ *                     copied at creation;
+ *   flags             LAGP_BATCH_SEL / LAGP_BATCH_STATUS when the calls will
+ *                     pass sel / status (they are required exactly then);
+ *   params->flags     must not contain LAGP_STRICT (it needs a host wait).
+ * A batch belongs to its design and must be destroyed before it. */
+#define LAGP_BATCH_SEL 1u
+#define LAGP_BATCH_STATUS 2u
+typedef struct lagp_batch lagp_batch;
+int lagp_batch_create(const lagp_design *design, int64_t T, const lagp_params *params, const int32_t *n_per,
+                      const int32_t *ncand_per, uint32_t flags, lagp_batch **out);
+
+/* Enqueue the batch for the locations XX (device T x p) with outputs as in
+ * lagp_predict.  Only kernel launches are enqueued -- no allocation, host
+ * synchronisation or memset -- so a caller may capture this call into its
+ * own HIP graph.  Calls on one batch share its workspace: do not overlap them. */
+int lagp_batch_enqueue(lagp_batch *batch, const double *XX, double *mean, double *s2, int32_t *df, double *var,
+                       int32_t *sel, int64_t sel_stride, int8_t *status, void *stream);
+
+/* As lagp_batch_enqueue, through a HIP graph the batch records on its own
+ * stream at the first call (and again whenever a pointer argument changes)
+ * and then launches on `stream` as a single graph launch. */
+int lagp_batch_launch_graph(lagp_batch *batch, const double *XX, double *mean, double *s2, int32_t *df,
+                            double *var, int32_t *sel, int64_t sel_stride, int8_t *status, void *stream);
+
+/* Number of buckets (design-kernel launches per replay) and workspace bytes. */
+int lagp_batch_info(const lagp_batch *batch, int32_t *buckets, size_t *workspace_bytes);
+
+/* Wait for the batch's work, free its memory and graph.  NULL is ignored. */
+void lagp_batch_destroy(lagp_batch *batch);
+
+/* Kernel-variant override for the greedy-design kernel, for tuning runs:
+ * threads 0 (tuned table or model), 256 or 512 (a candidate set above 2048
+ * always uses 512); coords -1 (table or model), 0 candidate coordinates in
+ * global memory, 1 in LDS when they fit.  Applies to later calls on `design`. */
+int lagp_design_set_variant(lagp_design *design, int32_t threads, int32_t coords);
+
 /* Device bytes of workspace lagp_predict needs for a batch of T locations
  * with the given maxima (for admission control by callers). */
 int lagp_workspace_bytes(const lagp_design *design, int64_t T, int32_t nmax, int32_t ncand_max,
                          size_t *out);
 
 /* Per-phase device timing.  While enabled, lagp_predict records HIP events on
- * its stream around each launch of its two phases: the candidate-set (kNN)
- * kernels and the greedy-design kernel.  lagp_phase_times waits for the
- * recorded events, returns the summed milliseconds and the number of
- * design-kernel launches since the last call, and clears the record. */
+ * its stream around the two phases of each chunk of locations: the
+ * candidate-set (kNN) kernels, then the greedy-design kernel launches (one
+ * per size bucket, plus in the mixed mode the FP64 prediction kernel and the
+ * FP64 redo launch).  lagp_phase_times waits for the recorded events, returns
+ * the summed milliseconds and the number of design-kernel bucket launches
+ * since the last call, and clears the record. */
 int lagp_timing_enable(lagp_design *design, int enable);
 int lagp_phase_times(lagp_design *design, double *knn_ms, double *design_ms, int64_t *design_launches);
 

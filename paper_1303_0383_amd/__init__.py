@@ -23,6 +23,7 @@ LAGP_OK, LAGP_E_INVAL, LAGP_E_NOMEM, LAGP_E_NODEVICE, LAGP_E_HIP, LAGP_E_BUDGET,
 LAGP_LOC_OK, LAGP_LOC_NOTPD = 0, 1
 LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32 = 0, 1
 LAGP_PTR_HOST, LAGP_STRICT = 1, 2
+LAGP_BATCH_SEL, LAGP_BATCH_STATUS = 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
@@ -48,9 +49,17 @@ _lib.lagp_predict_designs.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, _P, C.c_
 _lib.lagp_workspace_bytes.argtypes = [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
 _lib.lagp_timing_enable.argtypes = [_P, C.c_int]
 _lib.lagp_phase_times.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+_lib.lagp_batch_create.argtypes = [_P, C.c_int64, C.POINTER(lagp_params), _P, _P, C.c_uint32, C.POINTER(_P)]
+_lib.lagp_batch_enqueue.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.c_int64, _P, _P]
+_lib.lagp_batch_launch_graph.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.c_int64, _P, _P]
+_lib.lagp_batch_info.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]
+_lib.lagp_batch_destroy.argtypes = [_P]
+_lib.lagp_batch_destroy.restype = None
+_lib.lagp_design_set_variant.argtypes = [_P, C.c_int32, C.c_int32]
 _lib.lagp_last_error.restype = C.c_char_p
 for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
-           "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs"):
+           "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
+           "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -143,6 +152,40 @@ def lagp_workspace_bytes(design, T: int, nmax: int, ncand_max: int) -> int:
     return int(out.value)
 
 
+def lagp_batch_create(design, T: int, params: lagp_params, n_per=None, ncand_per=None, flags: int = 0):
+    """n_per / ncand_per: host int32 arrays of length T (or None)."""
+    hn = None if n_per is None else np.ascontiguousarray(np.asarray(n_per, dtype=np.int32))
+    hm = None if ncand_per is None else np.ascontiguousarray(np.asarray(ncand_per, dtype=np.int32))
+    out = _P()
+    _check(_lib.lagp_batch_create(design, T, C.byref(params), _ptr(hn), _ptr(hm), flags, C.byref(out)))
+    return out
+
+
+def lagp_batch_enqueue(batch, XX, mean, s2, df, var, sel, sel_stride: int, status, stream=None) -> None:
+    _check(_lib.lagp_batch_enqueue(batch, _ptr(XX), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel),
+                                   sel_stride, _ptr(status), _stream(stream)))
+
+
+def lagp_batch_launch_graph(batch, XX, mean, s2, df, var, sel, sel_stride: int, status, stream=None) -> None:
+    _check(_lib.lagp_batch_launch_graph(batch, _ptr(XX), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel),
+                                        sel_stride, _ptr(status), _stream(stream)))
+
+
+def lagp_batch_info(batch):
+    """(buckets, workspace_bytes)."""
+    b, w = C.c_int32(), C.c_size_t()
+    _check(_lib.lagp_batch_info(batch, C.byref(b), C.byref(w)))
+    return b.value, int(w.value)
+
+
+def lagp_batch_destroy(batch) -> None:
+    _lib.lagp_batch_destroy(batch)
+
+
+def lagp_design_set_variant(design, threads: int, coords: int) -> None:
+    _check(_lib.lagp_design_set_variant(design, threads, coords))
+
+
 def lagp_timing_enable(design, enable: bool) -> None:
     _check(_lib.lagp_timing_enable(design, 1 if enable else 0))
 
@@ -228,4 +271,55 @@ class Design:
         prm = lagp_params(n0, n, ncand, d, g, precision, LAGP_STRICT if strict else 0)
         lagp_predict(self._h, XX, T, prm, n_per, ncand_per, out.mean, out.s2, out.df, out.var, out.sel,
                      out.sel.shape[1], out.status, stream)
+        return out
+
+
+class Batch:
+    """Owns a lagp_batch: a fixed-shape batch of T locations (per-location
+    sizes fixed at creation) that runs as plain launches or one graph launch."""
+
+    def __init__(self, design: Design, T: int, n0: int, n: int, ncand: int, d: float, g: float, n_per=None,
+                 ncand_per=None, precision: int = LAGP_PREC_FP64, with_sel: bool = True, with_status: bool = True):
+        self.design = design
+        self.T = int(T)
+        self.nmax = int(np.max(n_per)) if n_per is not None else int(n)
+        prm = lagp_params(n0, n, ncand, d, g, precision, 0)
+        flags = (LAGP_BATCH_SEL if with_sel else 0) | (LAGP_BATCH_STATUS if with_status else 0)
+        self.with_sel, self.with_status = with_sel, with_status
+        self._h = lagp_batch_create(design.handle, self.T, prm, n_per, ncand_per, flags)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lagp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        return lagp_batch_info(self._h)
+
+    def outputs(self, device) -> Prediction:
+        import torch
+        T = self.T
+        return Prediction(mean=torch.empty(T, dtype=torch.float64, device=device),
+                          s2=torch.empty(T, dtype=torch.float64, device=device),
+                          df=torch.empty(T, dtype=torch.int32, device=device),
+                          var=torch.empty(T, dtype=torch.float64, device=device),
+                          sel=torch.empty((T, self.nmax), dtype=torch.int32, device=device) if self.with_sel else None,
+                          status=torch.empty(T, dtype=torch.int8, device=device) if self.with_status else None)
+
+    def run(self, XX, out: Optional[Prediction] = None, graph: bool = True, stream=None) -> Prediction:
+        XX = XX.contiguous()
+        out = out if out is not None else self.outputs(XX.device)
+        f = lagp_batch_launch_graph if graph else lagp_batch_enqueue
+        f(self._h, XX, out.mean, out.s2, out.df, out.var, out.sel, self.nmax if out.sel is None else out.sel.shape[1],
+          out.status, stream)
         return out

@@ -65,6 +65,8 @@ struct DesignArgs {
     int rlds, coords_lds;
     int nmax;
     unsigned int* counter;
+    const int32_t* order;    // nullable: work item -> location (else identity)
+    const uint32_t* count;   // nullable: number of work items, read on the device (else T)
 };
 
 // ---- exact division helpers
@@ -226,8 +228,9 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     for (;;) {
         if (tid == 0) ctl[0] = (int)atomicAdd(A.counter, 1u);
         __syncthreads();
-        const int64_t t = ctl[0];
-        if (t >= A.T) break;
+        const int64_t w = ctl[0];
+        if (w >= (A.count ? (int64_t)*A.count : A.T)) break;
+        const int64_t t = A.order ? A.order[w] : w;
         const int n = A.n_per ? A.n_per[t] : A.n;
         const int M = A.M_per ? A.M_per[t] : A.M;
         const int n0 = A.n0;
@@ -657,9 +660,13 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, i
     }
     const int rldsB = std::min<long long>(remB, avail / row_bytes);
     costB = (long long)pc * (nmax - 1) * (long long)crow_bytes + global_row_reads(nmax, rregB + rldsB) * (long long)row_bytes;
-    const bool cl = costA >= 0 && costA <= costB;
+    bool cl = costA >= 0 && costA <= costB;
+    if (plan->coords_pref == 0) cl = false;
+    else if (plan->coords_pref == 1 && costA >= 0) cl = true;
     plan->cpt = cpt;
     plan->threads = dt;
+    plan->p = p;
+    plan->lds_limit = max_lds;
     plan->mix = mix;
     plan->rreg = cl ? rregA : rregB;
     plan->rlds = cl ? rldsA : rldsB;
@@ -678,25 +685,31 @@ size_t design_workspace_bytes(const DesignPlan& plan)
     return plan.counter_bytes + plan.scratch_per_block * (size_t)plan.blocks;
 }
 
+// With `a` null the kernel variant's dynamic-LDS limit is raised (host-side
+// set-up, kept out of stream capture); otherwise the kernel is launched.
 template <int DT, int CPT, int P, bool CL, bool MIX>
-static int launch_design(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+static int launch_design(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     constexpr int RREG = rreg_for(DT, CPT, CL, MIX);
     auto kern = design_kernel<DT, CPT, RREG, P, CL, MIX>;
-    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)plan.lds_bytes) != hipSuccess) {
-        *err = "cannot reserve LDS for the design kernel";
-        return -2;
+    if (!a) {
+        // Plans of one variant may differ in LDS size and a captured graph may
+        // launch any of them: the limit is the device's.
+        if (!set_lds_limit((const void*)kern, plan.lds_limit)) {
+            *err = "cannot reserve LDS for the design kernel";
+            return -2;
+        }
+        return 0;
     }
-    hipLaunchKernelGGL(kern, dim3(plan.blocks), dim3(DT), plan.lds_bytes, stream, a);
+    hipLaunchKernelGGL(kern, dim3(plan.blocks), dim3(DT), plan.lds_bytes, stream, *a);
     if (hipGetLastError() != hipSuccess) { *err = "design kernel launch failed"; return -2; }
     return 0;
 }
 
 template <int DT, int CPT, bool CL, bool MIX>
-static int launch_design_p(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+static int launch_design_p(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    switch (a.p) {
+    switch (plan.p) {
     case 2: return launch_design<DT, CPT, 2, CL, MIX>(a, plan, stream, err);
     case 4: return launch_design<DT, CPT, 4, CL, MIX>(a, plan, stream, err);
     case 8: return launch_design<DT, CPT, 8, CL, MIX>(a, plan, stream, err);
@@ -705,7 +718,7 @@ static int launch_design_p(const DesignArgs& a, const DesignPlan& plan, hipStrea
 }
 
 template <int DT, int CPT>
-static int launch_design_c(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+static int launch_design_c(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     if (plan.mix)
         return plan.coords_lds ? launch_design_p<DT, CPT, true, true>(a, plan, stream, err)
@@ -715,7 +728,7 @@ static int launch_design_c(const DesignArgs& a, const DesignPlan& plan, hipStrea
 }
 
 template <int DT>
-static int launch_design_dt(const DesignArgs& a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+static int launch_design_dt(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     switch (plan.cpt) {
     case 1: return launch_design_c<DT, 1>(a, plan, stream, err);
@@ -724,6 +737,12 @@ static int launch_design_dt(const DesignArgs& a, const DesignPlan& plan, hipStre
     case 8: return launch_design_c<DT, 8>(a, plan, stream, err);
     default: return launch_design_c<DT, 8>(a, plan, stream, err);
     }
+}
+
+int design_prepare(const DesignPlan& plan, std::string* err)
+{
+    return plan.threads == 256 ? launch_design_dt<256>(nullptr, plan, nullptr, err)
+                               : launch_design_dt<512>(nullptr, plan, nullptr, err);
 }
 
 int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& plan, void* ws,
@@ -759,12 +778,11 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
     a.rlds = plan.rlds;
     a.coords_lds = plan.coords_lds ? 1 : 0;
     a.nmax = L.n;
-    if (hipMemsetAsync(a.counter, 0, sizeof(unsigned int), stream) != hipSuccess) {
-        *err = "hipMemsetAsync failed";
-        return -2;
-    }
-    return plan.threads == 256 ? launch_design_dt<256>(a, plan, stream, err)
-                               : launch_design_dt<512>(a, plan, stream, err);
+    a.order = L.order;
+    a.count = L.count;
+    fill_u32(a.counter, 1, 0u, stream);
+    return plan.threads == 256 ? launch_design_dt<256>(&a, plan, stream, err)
+                               : launch_design_dt<512>(&a, plan, stream, err);
 }
 
 }  // namespace lagp

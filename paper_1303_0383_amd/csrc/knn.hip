@@ -39,6 +39,7 @@ typedef unsigned __int128 u128;
 #define KNN_THREADS 256
 #define KNN_BINS 64
 #define KNN_TILE 256
+#define KNN_MAX_PASSES 18
 
 struct KnnState {
     uint64_t lo_hi, lo_lo;   // window lower bound (128-bit key)
@@ -97,6 +98,17 @@ __device__ __forceinline__ void exp_bin_window(int b, u128* lo, u128* hi)
     const u128 top = (u128)1 << 94;
     *lo = (b == 0) ? (u128)0 : ((u128)(uint64_t)(b + 971) << 83);
     *hi = (b == 63) ? top : ((u128)(uint64_t)(b + 972) << 83);
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
 }
 
 __global__ void knn_init_kernel(KnnState* st, uint32_t* hist, int64_t T)
@@ -218,7 +230,9 @@ __global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, int64_t T, int32
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
-    const int32_t M = M_per ? M_per[t] : M_all;
+    // Per-location sizes are clamped to the row length M_all (invalid sizes
+    // are rejected before launch, or flagged by the design kernel).
+    const int32_t M = M_per ? (M_per[t] < M_all ? M_per[t] : M_all) : M_all;
     KnnState s = st[t];
     if (s.settled) return;
     uint32_t* hg = hist + t * KNN_BINS;
@@ -331,11 +345,14 @@ knn_finalize_kernel(int64_t T, int32_t M_all, const int32_t* __restrict__ M_per,
     __shared__ uint64_t kh[1024], kl[1024];
     const int64_t t = blockIdx.x;
     if (t >= T) return;
-    const int32_t M = M_per ? M_per[t] : M_all;
+    const int32_t M = M_per ? (M_per[t] < M_all ? M_per[t] : M_all) : M_all;
     const KnnState s = st[t];
     const uint32_t nb = counts[2 * t], nk = counts[2 * t + 1];
     const int tid = threadIdx.x;
-    if (nb != s.below || nk != s.bucket || nb + nk < (uint32_t)M || nk > (uint32_t)bucket_max) {
+    if (!s.settled || nb != s.below || nk != s.bucket || nb + nk < (uint32_t)M || nk > (uint32_t)bucket_max) {
+        // Cannot happen for finite inputs; keep the row's indices valid and report.
+        int32_t* row = idx + t * idx_stride;
+        for (int e = tid; e < M; e += KNN_THREADS) row[e] = 0;
         if (tid == 0) atomicAdd(bad, 1);
         return;
     }
@@ -432,9 +449,32 @@ size_t knn_workspace_bytes(int64_t T, int32_t bucket_max)
     return b;
 }
 
+static void knn_lds(int p, size_t* lds_hist, size_t* lds_coll)
+{
+    const size_t lds_x = p <= 8 ? 0 : (size_t)KNN_THREADS * p * sizeof(double);
+    *lds_hist = (size_t)KNN_TILE * p * sizeof(double) + (size_t)KNN_BINS * KNN_THREADS * 2 + lds_x;
+    *lds_coll = (size_t)KNN_TILE * p * sizeof(double) + lds_x;
+}
+
+int knn_prepare(int p, size_t max_lds, std::string* err)
+{
+    size_t lds_hist, lds_coll;
+    knn_lds(p, &lds_hist, &lds_coll);
+    if (lds_hist > max_lds) { *err = "input dimension too large for the kNN tile"; return -1; }
+#define LAGP_KNN_ATTR(PP)                                                                              \
+    if (!set_lds_limit((const void*)knn_hist_kernel<PP>, max_lds) ||                                 \
+        !set_lds_limit((const void*)knn_collect_kernel<PP>, max_lds)) {                               \
+        *err = "cannot reserve LDS for the kNN kernels";                                              \
+        return -2;                                                                                     \
+    }
+    LAGP_DISPATCH_P(p, LAGP_KNN_ATTR);
+#undef LAGP_KNN_ATTR
+    return 0;
+}
+
 int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const int32_t* M_per,
             int32_t* idx, int64_t idx_stride, bool sorted, void* ws, size_t ws_bytes, hipStream_t stream,
-            int num_cu, size_t max_lds, std::string* err)
+            int num_cu, size_t max_lds, std::string* err, bool graph_safe)
 {
     if (T == 0) return 0;
     const int32_t bucket_max = 512;
@@ -461,44 +501,37 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     chunk = (chunk + KNN_TILE - 1) / KNN_TILE * KNN_TILE;
     split = (D.N + chunk - 1) / chunk;
 
-    const size_t lds_x = D.p <= 8 ? 0 : (size_t)KNN_THREADS * D.p * sizeof(double);
-    const size_t lds_hist = (size_t)KNN_TILE * D.p * sizeof(double) + (size_t)KNN_BINS * KNN_THREADS * 2 + lds_x;
-    const size_t lds_coll = (size_t)KNN_TILE * D.p * sizeof(double) + lds_x;
+    size_t lds_hist, lds_coll;
+    knn_lds(D.p, &lds_hist, &lds_coll);
     if (lds_hist > max_lds) { *err = "input dimension too large for the kNN tile"; return -1; }
-#define LAGP_KNN_ATTR(PP)                                                                              \
-    if (hipFuncSetAttribute((const void*)knn_hist_kernel<PP>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                            (int)lds_hist) != hipSuccess ||                                            \
-        hipFuncSetAttribute((const void*)knn_collect_kernel<PP>,                                       \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_coll) != hipSuccess) { \
-        *err = "cannot reserve LDS for the kNN kernels";                                              \
-        return -2;                                                                                     \
-    }
-    LAGP_DISPATCH_P(D.p, LAGP_KNN_ATTR);
-#undef LAGP_KNN_ATTR
+    if (!graph_safe && knn_prepare(D.p, max_lds, err)) return -2;
 
     hipLaunchKernelGGL(knn_init_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st, hist, T);
-    if (hipMemsetAsync(flags, 0, 16, stream) != hipSuccess) { *err = "hipMemsetAsync failed"; return -2; }
+    fill_u32(flags, 4, 0u, stream);
     const dim3 grid((unsigned)nblk, (unsigned)split);
-    for (int pass = 0; pass < 20; ++pass) {
+    // The first pass leaves a key window at most 2^93 wide and each later pass
+    // divides it by 64, so 17 passes always settle every location.  Without a
+    // host round trip (graph capture) all passes are launched; blocks whose
+    // locations have settled return at once.
+    for (int pass = 0; pass < KNN_MAX_PASSES; ++pass) {
 #define LAGP_KNN_HIST(PP) hipLaunchKernelGGL(knn_hist_kernel<PP>, grid, dim3(KNN_THREADS), lds_hist, stream, \
                                              D.Xsoa, D.N, D.p, XX, T, M, st, hist, chunk)
         LAGP_DISPATCH_P(D.p, LAGP_KNN_HIST);
 #undef LAGP_KNN_HIST
-        if (hipMemsetAsync(flags, 0, 4, stream) != hipSuccess) { *err = "hipMemsetAsync failed"; return -2; }
+        fill_u32(flags, 1, 0u, stream);
         hipLaunchKernelGGL(knn_decide_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st,
                            hist, T, M, M_per, bucket_max, flags);
-        uint32_t unsettled = 0;
-        if (hipMemcpyAsync(&unsettled, flags, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess) {
-            *err = "knn pass synchronisation failed";
-            return -2;
+        if (!graph_safe) {
+            uint32_t unsettled = 0;
+            if (hipMemcpyAsync(&unsettled, flags, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess) {
+                *err = "knn pass synchronisation failed";
+                return -2;
+            }
+            if (unsettled == 0) break;
         }
-        if (unsettled == 0) break;
     }
-    if (hipMemsetAsync(counts, 0, (size_t)T * 2 * sizeof(uint32_t), stream) != hipSuccess) {
-        *err = "hipMemsetAsync failed";
-        return -2;
-    }
+    fill_u32(counts, T * 2, 0u, stream);
 #define LAGP_KNN_COLL(PP) hipLaunchKernelGGL(knn_collect_kernel<PP>, grid, dim3(KNN_THREADS), lds_coll, stream, \
                                              D.Xsoa, D.N, D.p, XX, T, st, counts, idx, idx_stride, bucket, \
                                              bucket_max, chunk)
@@ -509,6 +542,7 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     if (sorted)
         hipLaunchKernelGGL(knn_sort_kernel, dim3((unsigned)T), dim3(KNN_THREADS), 0, stream, D.Xaos, D.p, XX,
                            T, M, idx, idx_stride);
+    if (graph_safe) return hipGetLastError() == hipSuccess ? 0 : -2;
     uint32_t bad = 0;
     if (hipMemcpyAsync(&bad, flags + 1, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {

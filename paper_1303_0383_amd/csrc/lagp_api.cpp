@@ -8,7 +8,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +32,10 @@ struct lagp_design {
     size_t ws_bytes = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;   // triples: before kNN, after kNN, after design
+    std::vector<int64_t> ev_launches;   // design-kernel launches per triple
+    std::string arch;                   // e.g. "gfx950"
+    int force_threads = 0;              // kernel-variant override (0: table or model)
+    int force_coords = -1;
 };
 
 namespace {
@@ -65,44 +72,6 @@ __global__ void aos_to_soa_kernel(const double* __restrict__ aos, double* __rest
     int64_t i = e / p;
     int k = (int)(e - i * p);
     soa[(int64_t)k * N + i] = aos[e];
-}
-
-// Rows idx[0..m-1] of src (row length w) into dst (m x w).
-template <typename T>
-__global__ void gather_rows_kernel(const T* __restrict__ src, int64_t w, const int64_t* __restrict__ idx, int64_t m,
-                                   T* __restrict__ dst)
-{
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m * w) return;
-    int64_t r = e / w, c = e - r * w;
-    dst[e] = src[idx[r] * w + c];
-}
-
-// Rows of src (m x w) back to rows idx[r] of dst (row stride dstride >= w).
-template <typename T>
-__global__ void scatter_rows_kernel(const T* __restrict__ src, int64_t w, const int64_t* __restrict__ idx, int64_t m,
-                                    T* __restrict__ dst, int64_t dstride)
-{
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m * w) return;
-    int64_t r = e / w, c = e - r * w;
-    dst[idx[r] * dstride + c] = src[e];
-}
-
-template <typename T>
-void gather_rows(const T* src, int64_t w, const int64_t* idx, int64_t m, T* dst, hipStream_t s)
-{
-    if (m * w == 0) return;
-    hipLaunchKernelGGL(gather_rows_kernel<T>, dim3((unsigned)((m * w + 255) / 256)), dim3(256), 0, s, src, w, idx, m,
-                       dst);
-}
-
-template <typename T>
-void scatter_rows(const T* src, int64_t w, const int64_t* idx, int64_t m, T* dst, int64_t dstride, hipStream_t s)
-{
-    if (m * w == 0 || !dst) return;
-    hipLaunchKernelGGL(scatter_rows_kernel<T>, dim3((unsigned)((m * w + 255) / 256)), dim3(256), 0, s, src, w, idx,
-                       m, dst, dstride);
 }
 
 int ensure_ws(lagp_design* d, size_t bytes, hipStream_t stream)
@@ -175,6 +144,8 @@ int lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, u
     e = hipGetDeviceProperties(&prop, d->device);
     if (e != hipSuccess) { delete d; return hip_fail("hipGetDeviceProperties", e); }
     d->num_cu = prop.multiProcessorCount;
+    d->arch = prop.gcnArchName;
+    d->arch = d->arch.substr(0, d->arch.find(':'));
     d->max_lds = prop.sharedMemPerBlock;
     const size_t bytes = (size_t)N * p * sizeof(double);
     if (hipMalloc(&d->Xaos, bytes) != hipSuccess || hipMalloc(&d->Xsoa, bytes) != hipSuccess ||
@@ -240,132 +211,142 @@ int lagp_knn(const lagp_design* design, const double* XX, int64_t T, int32_t M, 
     return LAGP_OK;
 }
 
-static int plan_for(const lagp_design* d, int32_t nmax, int32_t Mmax, const lagp_params* prm, int64_t tc,
-                    lagp::DesignPlan* plan, size_t* knn_bytes, size_t* cand_bytes, size_t* design_bytes)
+}  // extern "C"
+
+// ------------------------------------------------------------ batch planning
+//
+// A batch is planned once from host-side sizes: every location is checked,
+// locations are grouped by size class (candidate-set size rounded up to a
+// power of two >= 256, design size rounded up to a power of two >= 32) so
+// that each group runs a kernel variant sized for it, and each group is
+// ordered by decreasing modelled cost (longest first) so that the persistent
+// workgroups finish together.  Enqueueing a plan launches kernels only: no
+// allocation, no host synchronisation and no memset, so it can be captured
+// into a HIP graph.
+namespace {
+
+struct Bucket {
+    int32_t nmax = 0, Mmax = 0;
+    int64_t first = 0, count = 0;   // range of the chunk's work list
+    lagp::DesignPlan plan;
+};
+
+struct Chunk {
+    int64_t t0 = 0, T = 0;
+    int32_t nmax = 0, Mmax = 0;
+    std::vector<Bucket> buckets;
+    lagp::DesignPlan redo;   // FP64 plan for locations the mixed mode could not finish
+};
+
+struct Plan {
+    lagp_params prm{};
+    int64_t T = 0;
+    int32_t nmax = 0, Mmax = 0;
+    bool uneven = false, mix = false, own_sel = false, own_status = false;
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> order;   // chunk-relative locations, chunk c at [t0, t0 + T)
+    // workspace layout
+    size_t knn_b = 0, cand_b = 0, design_b = 0, order_b = 0, sel_b = 0, status_b = 0, redo_b = 0, total = 0;
+};
+
+int size_class(int32_t v, int32_t lo)
+{
+    int c = lo;
+    while (c < v) c <<= 1;
+    return c;
+}
+
+// ---- tuned kernel variants: text table "arch precision mclass nclass threads coords"
+struct TuneEntry {
+    std::string arch;
+    int prec, mclass, nclass, threads, coords;
+};
+
+std::vector<TuneEntry>& tune_table()
+{
+    static std::vector<TuneEntry> table;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        std::string path;
+        if (const char* e = getenv("LAGP_TUNE_TABLE")) {
+            path = e;
+        } else {
+            Dl_info info;
+            if (dladdr((const void*)&lagp_version, &info) && info.dli_fname) {
+                path = info.dli_fname;
+                const size_t k = path.rfind('/');
+                path = (k == std::string::npos ? std::string(".") : path.substr(0, k)) + "/tune/table.txt";
+            }
+        }
+        FILE* f = path.empty() ? nullptr : fopen(path.c_str(), "r");
+        if (!f) return;
+        char line[512];
+        while (fgets(line, sizeof line, f)) {
+            if (line[0] == '#') continue;
+            char arch[64];
+            TuneEntry t;
+            if (sscanf(line, "%63s %d %d %d %d %d", arch, &t.prec, &t.mclass, &t.nclass, &t.threads, &t.coords) == 6) {
+                t.arch = arch;
+                table.push_back(t);
+            }
+        }
+        fclose(f);
+    });
+    return table;
+}
+
+void choose_variant(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, lagp::DesignPlan* plan)
+{
+    plan->threads = 256;
+    plan->coords_pref = -1;
+    if (d->force_threads || d->force_coords >= 0) {
+        if (d->force_threads) plan->threads = d->force_threads;
+        plan->coords_pref = d->force_coords;
+        return;
+    }
+    const int mc = size_class(Mmax, 256), nc = size_class(nmax, 32);
+    for (const TuneEntry& t : tune_table())
+        if (t.arch == d->arch && t.prec == prec && t.mclass == mc && t.nclass == nc) {
+            plan->threads = t.threads;
+            plan->coords_pref = t.coords;
+            return;
+        }
+}
+
+int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int32_t n0, lagp::DesignPlan* plan)
 {
     std::string err;
-    const char* thr = getenv("LAGP_DESIGN_THREADS");
-    plan->threads = (thr && atoi(thr) == 512) ? 512 : 256;
-    if (lagp::design_plan(d->dev, nmax, Mmax, prm->n0, prm->precision, d->num_cu, d->max_lds, plan, &err))
+    choose_variant(d, prec, nmax, Mmax, plan);
+    if (lagp::design_plan(d->dev, nmax, Mmax, n0, prec, d->num_cu, d->max_lds, plan, &err))
         return fail(LAGP_E_INVAL, err);
-    *knn_bytes = lagp::align256(lagp::knn_workspace_bytes(tc, kBucketMax));
-    *cand_bytes = lagp::align256((size_t)tc * Mmax * sizeof(int32_t));
-    *design_bytes = lagp::align256(lagp::design_workspace_bytes(*plan));
     return LAGP_OK;
 }
 
-int lagp_workspace_bytes(const lagp_design* design, int64_t T, int32_t nmax, int32_t ncand_max, size_t* out)
+// Checks parameters and per-location sizes (host arrays, nullable) and builds the plan.
+int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
+               bool have_sel, bool have_status, Plan* P)
 {
-    if (!design || !out) return fail(LAGP_E_INVAL, "NULL argument");
-    if (T < 0 || nmax < 1 || ncand_max < nmax) return fail(LAGP_E_INVAL, "bad sizes");
-    lagp_params prm = {1, nmax, ncand_max, 1.0, 0.0, 0, 0};
-    lagp::DesignPlan plan;
-    size_t a, b, c;
-    int rc = plan_for(design, nmax, ncand_max, &prm, std::min(kChunk, std::max<int64_t>(T, 1)), &plan, &a, &b, &c);
-    if (rc) return rc;
-    *out = a + b + c;
-    return LAGP_OK;
-}
-
-int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
-                 const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
-                 int32_t* sel, int64_t sel_stride, int8_t* status, void* stream);
-
-// Re-run the locations `idx` in FP64 and scatter their outputs back.
-static int redo_fp64(lagp_design* d, const double* XX, const lagp_params* prm, const int32_t* n_per,
-                     const int32_t* ncand_per, const std::vector<int64_t>& idx, int32_t nmax, double* mean, double* s2,
-                     int32_t* df, double* var, int32_t* sel, int64_t sel_stride, int8_t* status, hipStream_t s)
-{
-    const int64_t m = (int64_t)idx.size();
-    const int p = d->dev.p;
-    size_t bytes = lagp::align256(m * sizeof(int64_t)) + lagp::align256(m * p * sizeof(double)) +
-                   2 * lagp::align256(m * sizeof(int32_t)) + 3 * lagp::align256(m * sizeof(double)) +
-                   lagp::align256(m * sizeof(int32_t)) + lagp::align256(m * nmax * sizeof(int32_t)) +
-                   lagp::align256(m);
-    char* buf = nullptr;
-    hipError_t e = hipMalloc(&buf, bytes);
-    if (e != hipSuccess) { (void)hipGetLastError(); return fail(LAGP_E_NOMEM, "FP64 redo buffer allocation failed"); }
-    char* q = buf;
-    auto take = [&](size_t b) { char* r = q; q += lagp::align256(b); return r; };
-    int64_t* di = (int64_t*)take(m * sizeof(int64_t));
-    double* xx = (double*)take(m * p * sizeof(double));
-    int32_t* np_ = (int32_t*)take(m * sizeof(int32_t));
-    int32_t* mp_ = (int32_t*)take(m * sizeof(int32_t));
-    double* me = (double*)take(m * sizeof(double));
-    double* sc = (double*)take(m * sizeof(double));
-    double* va = (double*)take(m * sizeof(double));
-    int32_t* dfo = (int32_t*)take(m * sizeof(int32_t));
-    int32_t* so = (int32_t*)take(m * nmax * sizeof(int32_t));
-    int8_t* sto = (int8_t*)take(m);
-    int rc = LAGP_OK;
-    e = hipMemcpyAsync(di, idx.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) { rc = hip_fail("redo index copy", e); goto done; }
-    gather_rows<double>(XX, p, di, m, xx, s);
-    if (n_per) gather_rows<int32_t>(n_per, 1, di, m, np_, s);
-    if (ncand_per) gather_rows<int32_t>(ncand_per, 1, di, m, mp_, s);
-    {
-        lagp_params q64 = *prm;
-        q64.precision = LAGP_PREC_FP64;
-        q64.flags = 0;
-        rc = lagp_predict(d, xx, m, &q64, n_per ? np_ : nullptr, ncand_per ? mp_ : nullptr, me, sc, dfo, va, so, nmax,
-                          sto, s);
-    }
-    if (rc) goto done;
-    scatter_rows<double>(me, 1, di, m, mean, 1, s);
-    scatter_rows<double>(sc, 1, di, m, s2, 1, s);
-    scatter_rows<double>(va, 1, di, m, var, 1, s);
-    scatter_rows<int32_t>(dfo, 1, di, m, df, 1, s);
-    scatter_rows<int8_t>(sto, 1, di, m, status, 1, s);
-    scatter_rows<int32_t>(so, nmax, di, m, sel, sel_stride, s);
-    e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e != hipSuccess) rc = hip_fail("FP64 redo", e);
-done:
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(buf);
-    return rc;
-}
-
-int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
-                 const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
-                 int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
-{
-    if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
-    if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
-    const int64_t N = design->dev.N;
+    const int64_t N = d->dev.N;
     if (!(prm->d > 0.0) || !isfinite(prm->d)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
     if (!(prm->g >= 0.0) || !isfinite(prm->g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
     if (prm->precision != LAGP_PREC_FP64 && prm->precision != LAGP_PREC_SCORE_FP32)
         return fail(LAGP_E_INVAL, "unsupported precision mode");
     if (prm->flags & ~(uint32_t)LAGP_STRICT) return fail(LAGP_E_INVAL, "unknown flag");
     if (prm->n0 < 1) return fail(LAGP_E_INVAL, "n0 must be >= 1");
-    if (!n_per && (prm->n < prm->n0)) return fail(LAGP_E_INVAL, "n must be >= n0");
-    if (!ncand_per && (prm->ncand < 1 || prm->ncand > N)) return fail(LAGP_E_INVAL, "ncand must be in [1, N]");
-    if (!n_per && !ncand_per && prm->ncand < prm->n) return fail(LAGP_E_INVAL, "ncand must be >= n");
-    if (T == 0) return LAGP_OK;
-    if (!XX || !mean || !s2) return fail(LAGP_E_INVAL, "XX, mean and s2 are required");
-    int rc = check_device(design);
-    if (rc) return rc;
-    const void* devptrs[] = {XX, mean, s2, df, var, sel, status, n_per, ncand_per};
-    for (const void* q : devptrs)
-        if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
-    hipStream_t s = (hipStream_t)stream;
-
-    // Per-location sizes: validate on the host and take maxima.
+    if (!hn && (prm->n < prm->n0)) return fail(LAGP_E_INVAL, "n must be >= n0");
+    if (!hm && (prm->ncand < 1 || prm->ncand > N)) return fail(LAGP_E_INVAL, "ncand must be in [1, N]");
+    if (!hn && !hm && prm->ncand < prm->n) return fail(LAGP_E_INVAL, "ncand must be >= n");
+    P->prm = *prm;
+    P->T = T;
+    P->uneven = hn || hm;
+    P->mix = prm->precision == LAGP_PREC_SCORE_FP32;
     int32_t nmax = prm->n, Mmax = prm->ncand;
-    if (n_per || ncand_per) {
-        std::vector<int32_t> hn(n_per ? T : 0), hm(ncand_per ? T : 0);
-        hipError_t e = hipSuccess;
-        if (n_per) e = hipMemcpyAsync(hn.data(), n_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess && ncand_per)
-            e = hipMemcpyAsync(hm.data(), ncand_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail("per-location size copy", e);
+    if (P->uneven) {
         nmax = 0;
         Mmax = 0;
         for (int64_t t = 0; t < T; ++t) {
-            const int32_t nt = n_per ? hn[t] : prm->n;
-            const int32_t mt = ncand_per ? hm[t] : prm->ncand;
+            const int32_t nt = hn ? hn[t] : prm->n;
+            const int32_t mt = hm ? hm[t] : prm->ncand;
             if (nt < prm->n0 || mt < nt || mt > N)
                 return fail(LAGP_E_INVAL, "location " + std::to_string(t) + ": need n0 <= n <= ncand <= N");
             nmax = std::max(nmax, nt);
@@ -374,96 +355,303 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     }
     if (Mmax > 4096) return fail(LAGP_E_INVAL, "ncand above 4096 is not supported");
     if (nmax > 1024) return fail(LAGP_E_INVAL, "n above 1024 is not supported");
-    if (sel && sel_stride < nmax) return fail(LAGP_E_INVAL, "sel_stride must be >= n");
-
-    lagp_design* d = const_cast<lagp_design*>(design);
-    const int64_t tc_max = std::min(kChunk, T);
-    lagp::DesignPlan plan;
-    size_t kb, cb, db;
-    rc = plan_for(d, nmax, Mmax, prm, tc_max, &plan, &kb, &cb, &db);
-    if (rc) return rc;
-    const bool mix = prm->precision == LAGP_PREC_SCORE_FP32;
-    if (mix && lagp::predict_lds_bytes(nmax) > d->max_lds)
+    if (P->mix && lagp::predict_lds_bytes(nmax) > d->max_lds)
         return fail(LAGP_E_INVAL, "n too large for the FP64 prediction kernel of the mixed mode");
-    // The mixed mode needs the selections for its FP64 prediction pass.
-    const size_t sb = (mix && !sel) ? lagp::align256((size_t)tc_max * nmax * sizeof(int32_t)) : 0;
-    // ... and the per-location status to find locations to redo in FP64.
-    const size_t stb = (mix && !status) ? lagp::align256((size_t)T) : 0;
-    if (getenv("LAGP_VERBOSE"))
-        fprintf(stderr,
-                "[lagp] plan: n=%d ncand=%d p=%d threads=%d slots/thread=%d rows: reg=%d lds=%d global=%d "
-                "coords_lds=%d lds=%zu B global_row_reads/loc=%lld workspace=%zu B\n",
-                nmax, Mmax, d->dev.p, plan.threads, plan.cpt, plan.rreg, plan.rlds, plan.rglob,
-                (int)plan.coords_lds, plan.lds_bytes, plan.global_row_reads, kb + cb + db + sb);
-    rc = ensure_ws(d, kb + cb + db + sb + stb, s);
-    if (rc) return rc;
-    char* base = (char*)d->ws;
-    void* knn_ws = base;
-    int32_t* cand = (int32_t*)(base + kb);
-    void* des_ws = base + kb + cb;
-    int32_t* sel_ws = sb ? (int32_t*)(base + kb + cb + db) : nullptr;
-    int8_t* st_all = status ? status : (stb ? (int8_t*)(base + kb + cb + db + sb) : nullptr);
-
+    P->nmax = nmax;
+    P->Mmax = Mmax;
+    P->own_sel = P->mix && !have_sel;
+    P->own_status = P->mix && !have_status;
+    const int64_t tc_max = std::min(kChunk, std::max<int64_t>(T, 1));
+    size_t design_b = 0;
+    if (P->uneven) P->order.resize(T);
     for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
-        const int64_t tc = std::min(kChunk, T - t0);
+        Chunk c;
+        c.t0 = t0;
+        c.T = std::min(kChunk, T - t0);
+        c.nmax = 0;
+        c.Mmax = 0;
+        if (!P->uneven) {
+            Bucket b;
+            b.nmax = c.nmax = nmax;
+            b.Mmax = c.Mmax = Mmax;
+            b.first = 0;
+            b.count = c.T;
+            c.buckets.push_back(b);
+        } else {
+            // group by (candidate class, design class), largest classes first
+            std::vector<std::pair<int64_t, int64_t>> key(c.T);   // (class key, location)
+            for (int64_t k = 0; k < c.T; ++k) {
+                const int64_t t = t0 + k;
+                const int32_t nt = hn ? hn[t] : prm->n, mt = hm ? hm[t] : prm->ncand;
+                c.nmax = std::max(c.nmax, nt);
+                c.Mmax = std::max(c.Mmax, mt);
+                key[k] = {-((int64_t)size_class(mt, 256) << 16 | size_class(nt, 32)), k};
+            }
+            auto cost = [&](int64_t k) {
+                const int64_t t = t0 + k;
+                const double nt = hn ? hn[t] : prm->n, mt = hm ? hm[t] : prm->ncand;
+                return nt * nt * mt;
+            };
+            std::stable_sort(key.begin(), key.end(), [&](const auto& a, const auto& b) {
+                if (a.first != b.first) return a.first < b.first;
+                const double ca = cost(a.second), cb = cost(b.second);
+                if (ca != cb) return ca > cb;
+                return a.second < b.second;
+            });
+            for (int64_t k = 0; k < c.T;) {
+                int64_t e = k;
+                Bucket b;
+                while (e < c.T && key[e].first == key[k].first) {
+                    const int64_t t = t0 + key[e].second;
+                    b.nmax = std::max(b.nmax, hn ? hn[t] : prm->n);
+                    b.Mmax = std::max(b.Mmax, hm ? hm[t] : prm->ncand);
+                    P->order[t0 + e] = (int32_t)key[e].second;
+                    ++e;
+                }
+                b.first = k;
+                b.count = e - k;
+                c.buckets.push_back(b);
+                k = e;
+            }
+        }
+        for (Bucket& b : c.buckets) {
+            int rc = plan_design(d, prm->precision, b.nmax, b.Mmax, prm->n0, &b.plan);
+            if (rc) return rc;
+            design_b = std::max(design_b, lagp::design_workspace_bytes(b.plan));
+        }
+        if (P->mix) {
+            int rc = plan_design(d, LAGP_PREC_FP64, c.nmax, c.Mmax, prm->n0, &c.redo);
+            if (rc) return rc;
+            design_b = std::max(design_b, lagp::design_workspace_bytes(c.redo));
+        }
+        P->chunks.push_back(c);
+    }
+    P->knn_b = lagp::align256(lagp::knn_workspace_bytes(tc_max, kBucketMax));
+    P->cand_b = lagp::align256((size_t)tc_max * Mmax * sizeof(int32_t));
+    P->design_b = lagp::align256(design_b);
+    P->order_b = P->uneven ? lagp::align256((size_t)T * sizeof(int32_t)) : 0;
+    P->sel_b = P->own_sel ? lagp::align256((size_t)tc_max * nmax * sizeof(int32_t)) : 0;
+    P->status_b = P->own_status ? lagp::align256((size_t)T) : 0;
+    P->redo_b = P->mix ? lagp::align256((size_t)tc_max * sizeof(int32_t)) + 256 : 0;
+    P->total = P->knn_b + P->cand_b + P->design_b + P->order_b + P->sel_b + P->status_b + P->redo_b;
+    if (getenv("LAGP_VERBOSE"))
+        for (const Chunk& c : P->chunks)
+            for (const Bucket& b : c.buckets)
+                fprintf(stderr,
+                        "[lagp] bucket: locations=%lld n<=%d ncand<=%d p=%d threads=%d slots/thread=%d rows: reg=%d "
+                        "lds=%d global=%d coords_lds=%d lds=%zu B global_row_reads/loc=%lld workspace=%zu B\n",
+                        (long long)b.count, b.nmax, b.Mmax, d->dev.p, b.plan.threads, b.plan.cpt, b.plan.rreg,
+                        b.plan.rlds, b.plan.rglob, (int)b.plan.coords_lds, b.plan.lds_bytes,
+                        b.plan.global_row_reads, P->total);
+    return LAGP_OK;
+}
+
+// Host-side kernel set-up for every variant the plan launches.
+int prepare_plan(const lagp_design* d, const Plan& P)
+{
+    std::string err;
+    if (lagp::knn_prepare(d->dev.p, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    for (const Chunk& c : P.chunks) {
+        for (const Bucket& b : c.buckets)
+            if (lagp::design_prepare(b.plan, &err)) return fail(LAGP_E_HIP, err);
+        if (P.mix && lagp::design_prepare(c.redo, &err)) return fail(LAGP_E_HIP, err);
+    }
+    if (P.mix && lagp::predict_prepare(P.nmax, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    return LAGP_OK;
+}
+
+struct Outputs {
+    double* mean;
+    double* s2;
+    int32_t* df;
+    double* var;
+    int32_t* sel;
+    int64_t sel_stride;
+    int8_t* status;
+};
+
+__global__ void collect_failed_kernel(const int8_t* __restrict__ status, int64_t T, int32_t* __restrict__ list,
+                                      uint32_t* __restrict__ count)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T && status[t] != LAGP_LOC_OK) list[atomicAdd(count, 1u)] = (int32_t)t;
+}
+
+// Enqueues the whole plan on stream s.  ws holds P.total bytes; order_dev is
+// the uploaded work list (uneven plans); n_per / ncand_per are device arrays.
+int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_dev, const int32_t* n_per,
+                 const int32_t* ncand_per, const double* XX, const Outputs& o, hipStream_t s, bool graph_safe)
+{
+    char* q = ws;
+    void* knn_ws = q;                  q += P.knn_b;
+    int32_t* cand = (int32_t*)q;       q += P.cand_b;
+    void* des_ws = q;                  q += P.design_b;
+    q += P.order_b;                    // (order_dev lives here for lagp_predict)
+    int32_t* sel_ws = (int32_t*)q;     q += P.sel_b;
+    int8_t* st_ws = (int8_t*)q;        q += P.status_b;
+    int32_t* redo_list = (int32_t*)q;
+    uint32_t* redo_count = (uint32_t*)(q + (P.redo_b ? P.redo_b - 256 : 0));
+    const int p = d->dev.p;
+    const bool timing = d->timing && !graph_safe;
+    for (const Chunk& c : P.chunks) {
         std::string err;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        if (d->timing) {
+        if (timing) {
             for (int k = 0; k < 3; ++k) {
                 hipError_t e = hipEventCreate(&ev[k]);
                 if (e != hipSuccess) return hip_fail("hipEventCreate", e);
                 d->ev.push_back(ev[k]);
             }
+            d->ev_launches.push_back((int64_t)c.buckets.size());
             (void)hipEventRecord(ev[0], s);
         }
-        int r = lagp::knn_run(d->dev, XX + t0 * d->dev.p, tc, Mmax, ncand_per ? ncand_per + t0 : nullptr, cand,
-                              Mmax, false, knn_ws, kb, s, d->num_cu, d->max_lds, &err);
+        const double* xx = XX + c.t0 * p;
+        int r = lagp::knn_run(d->dev, xx, c.T, P.Mmax, ncand_per ? ncand_per + c.t0 : nullptr, cand, P.Mmax, false,
+                              knn_ws, P.knn_b, s, d->num_cu, d->max_lds, &err, graph_safe);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-        if (d->timing) (void)hipEventRecord(ev[1], s);
+        if (timing) (void)hipEventRecord(ev[1], s);
         lagp::DesignLaunch L;
-        L.XX = XX + t0 * d->dev.p;
-        L.T = tc;
+        L.XX = xx;
         L.cand = cand;
-        L.cand_stride = Mmax;
-        L.n_per = n_per ? n_per + t0 : nullptr;
-        L.M_per = ncand_per ? ncand_per + t0 : nullptr;
-        L.n0 = prm->n0;
-        L.n = nmax;
-        L.M = Mmax;
-        L.theta = prm->d;
-        L.eta = prm->g;
-        L.precision = prm->precision;
-        L.mean = mean + t0;
-        L.s2 = s2 + t0;
-        L.df = df ? df + t0 : nullptr;
-        L.var = var ? var + t0 : nullptr;
-        L.sel = sel ? sel + t0 * sel_stride : sel_ws;
-        L.sel_stride = sel ? sel_stride : nmax;
-        L.status = st_all ? st_all + t0 : nullptr;
-        r = lagp::design_run(d->dev, L, plan, des_ws, db, s, &err);
-        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-        if (mix) {
-            r = lagp::predict_run(d->dev, L.XX, tc, L.sel, L.sel_stride, L.n_per, nmax, prm->d, prm->g, L.mean, L.s2,
-                                  L.df, L.var, L.status, d->max_lds, s, &err);
+        L.cand_stride = P.Mmax;
+        L.n_per = n_per ? n_per + c.t0 : nullptr;
+        L.M_per = ncand_per ? ncand_per + c.t0 : nullptr;
+        L.n0 = P.prm.n0;
+        L.theta = P.prm.d;
+        L.eta = P.prm.g;
+        L.mean = o.mean + c.t0;
+        L.s2 = o.s2 + c.t0;
+        L.df = o.df ? o.df + c.t0 : nullptr;
+        L.var = o.var ? o.var + c.t0 : nullptr;
+        L.sel = o.sel ? o.sel + c.t0 * o.sel_stride : sel_ws;
+        L.sel_stride = o.sel ? o.sel_stride : P.nmax;
+        L.status = o.status ? o.status + c.t0 : (P.own_status ? st_ws + c.t0 : nullptr);
+        for (const Bucket& b : c.buckets) {
+            L.precision = P.prm.precision;
+            L.T = b.count;
+            L.n = b.nmax;
+            L.M = b.Mmax;
+            L.order = order_dev ? order_dev + c.t0 + b.first : nullptr;
+            r = lagp::design_run(d->dev, L, b.plan, des_ws, P.design_b, s, &err);
             if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
         }
-        if (d->timing) (void)hipEventRecord(ev[2], s);
-    }
-    if (mix) {
-        // FP32 ranking can lose positive definiteness where FP64 keeps it (tiny
-        // nuggets, near-duplicate neighbours): redo those locations in FP64.
-        std::vector<int8_t> hs(T);
-        hipError_t e = hipMemcpyAsync(hs.data(), st_all, T, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail("status copy", e);
-        std::vector<int64_t> redo;
-        for (int64_t t = 0; t < T; ++t)
-            if (hs[t] != LAGP_LOC_OK) redo.push_back(t);
-        if (!redo.empty()) {
-            rc = redo_fp64(d, XX, prm, n_per, ncand_per, redo, nmax, mean, s2, df, var, sel, sel_stride, status, s);
-            if (rc) return rc;
+        if (P.mix) {
+            r = lagp::predict_run(d->dev, xx, c.T, L.sel, L.sel_stride, L.n_per, c.nmax, P.prm.d, P.prm.g, L.mean,
+                                  L.s2, L.df, L.var, L.status, d->max_lds, s, &err);
+            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+            // FP32 ranking can lose positive definiteness where FP64 keeps it
+            // (tiny nuggets, near-duplicate neighbours): the locations that
+            // failed are redone in FP64 from a device-side list.
+            lagp::fill_u32(redo_count, 1, 0u, s);
+            hipLaunchKernelGGL(collect_failed_kernel, dim3((unsigned)((c.T + 255) / 256)), dim3(256), 0, s, L.status,
+                               c.T, redo_list, redo_count);
+            L.precision = LAGP_PREC_FP64;
+            L.T = c.T;
+            L.n = c.nmax;
+            L.M = c.Mmax;
+            L.order = redo_list;
+            L.count = redo_count;
+            r = lagp::design_run(d->dev, L, c.redo, des_ws, P.design_b, s, &err);
+            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+            L.count = nullptr;
         }
+        if (timing) (void)hipEventRecord(ev[2], s);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail("launch", e);
+    return LAGP_OK;
+}
+
+int check_outputs(const Outputs& o, int32_t nmax)
+{
+    if (!o.mean || !o.s2) return fail(LAGP_E_INVAL, "mean and s2 are required");
+    if (o.sel && o.sel_stride < nmax) return fail(LAGP_E_INVAL, "sel_stride must be >= n");
+    const void* devptrs[] = {o.mean, o.s2, o.df, o.var, o.sel, o.status};
+    for (const void* q : devptrs)
+        if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
+    return LAGP_OK;
+}
+
+}  // namespace
+
+struct lagp_batch {
+    lagp_design* design = nullptr;
+    Plan plan;
+    bool have_sel = false, have_status = false;
+    char* mem = nullptr;          // workspace, then the work list and size arrays
+    int32_t* order = nullptr;
+    int32_t* n_per = nullptr;
+    int32_t* ncand_per = nullptr;
+    hipStream_t cap = nullptr;    // capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key[8] = {};      // pointers the captured graph was recorded with
+};
+
+extern "C" {
+
+int lagp_workspace_bytes(const lagp_design* design, int64_t T, int32_t nmax, int32_t ncand_max, size_t* out)
+{
+    if (!design || !out) return fail(LAGP_E_INVAL, "NULL argument");
+    if (T < 0 || nmax < 1 || ncand_max < nmax) return fail(LAGP_E_INVAL, "bad sizes");
+    lagp_params prm = {1, nmax, ncand_max, 1.0, 0.0, 0, 0};
+    if (ncand_max > design->dev.N) return fail(LAGP_E_INVAL, "ncand above N");
+    Plan P;
+    int rc = build_plan(design, &prm, std::max<int64_t>(T, 1), nullptr, nullptr, true, true, &P);
+    if (rc) return rc;
+    *out = P.total;
+    return LAGP_OK;
+}
+
+int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                 const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
+                 int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+{
+    if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
+    if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
+    if (T == 0) {
+        Plan P;
+        return build_plan(design, prm, 0, nullptr, nullptr, true, true, &P);
+    }
+    if (!XX || !mean || !s2) return fail(LAGP_E_INVAL, "XX, mean and s2 are required");
+    int rc = check_device(design);
+    if (rc) return rc;
+    const void* devptrs[] = {XX, n_per, ncand_per};
+    for (const void* q : devptrs)
+        if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
+    const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
+    hipStream_t s = (hipStream_t)stream;
+
+    // Per-location sizes come to the host for checking and bucketing.
+    std::vector<int32_t> hn(n_per ? T : 0), hm(ncand_per ? T : 0);
+    if (n_per || ncand_per) {
+        hipError_t e = hipSuccess;
+        if (n_per) e = hipMemcpyAsync(hn.data(), n_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && ncand_per)
+            e = hipMemcpyAsync(hm.data(), ncand_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail("per-location size copy", e);
+    }
+    Plan P;
+    rc = build_plan(design, prm, T, n_per ? hn.data() : nullptr, ncand_per ? hm.data() : nullptr, sel != nullptr,
+                    status != nullptr, &P);
+    if (rc) return rc;
+    rc = check_outputs(o, P.nmax);
+    if (rc) return rc;
+    lagp_design* d = const_cast<lagp_design*>(design);
+    rc = ensure_ws(d, P.total, s);
+    if (rc) return rc;
+    rc = prepare_plan(d, P);
+    if (rc) return rc;
+    int32_t* order_dev = nullptr;
+    if (P.uneven) {
+        order_dev = (int32_t*)((char*)d->ws + P.knn_b + P.cand_b + P.design_b);
+        hipError_t e = hipMemcpyAsync(order_dev, P.order.data(), T * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // P.order is released on return
+        if (e != hipSuccess) return hip_fail("work list copy", e);
+    }
+    rc = enqueue_plan(d, P, (char*)d->ws, order_dev, n_per, ncand_per, XX, o, s, false);
+    if (rc) return rc;
     if (prm->flags & LAGP_STRICT) {
         if (!status) return fail(LAGP_E_INVAL, "strict mode needs the status output");
         std::vector<int8_t> hs(T);
@@ -473,6 +661,135 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         for (int8_t v : hs)
             if (v != LAGP_LOC_OK) return fail(LAGP_E_NOTPD, "some location's local covariance was not positive definite");
     }
+    return LAGP_OK;
+}
+
+// ---------------------------------------------------------------- batches
+int lagp_batch_create(const lagp_design* design, int64_t T, const lagp_params* prm, const int32_t* n_per,
+                      const int32_t* ncand_per, uint32_t flags, lagp_batch** out)
+{
+    if (!out) return fail(LAGP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
+    if (T < 1) return fail(LAGP_E_INVAL, "T must be >= 1");
+    if (prm->flags & LAGP_STRICT) return fail(LAGP_E_INVAL, "strict mode needs a host synchronisation; use lagp_predict");
+    if (flags & ~(LAGP_BATCH_SEL | LAGP_BATCH_STATUS)) return fail(LAGP_E_INVAL, "unknown flag");
+    int rc = check_device(design);
+    if (rc) return rc;
+    if ((n_per && is_device_ptr(n_per)) || (ncand_per && is_device_ptr(ncand_per)))
+        return fail(LAGP_E_INVAL, "n_per and ncand_per must be host arrays");
+    lagp_batch* b = new lagp_batch();
+    b->design = const_cast<lagp_design*>(design);
+    b->have_sel = flags & LAGP_BATCH_SEL;
+    b->have_status = flags & LAGP_BATCH_STATUS;
+    rc = build_plan(design, prm, T, n_per, ncand_per, b->have_sel, b->have_status, &b->plan);
+    if (rc) { delete b; return rc; }
+    const Plan& P = b->plan;
+    const size_t sizes_b = lagp::align256((size_t)T * sizeof(int32_t));
+    const size_t bytes = P.total + (n_per ? sizes_b : 0) + (ncand_per ? sizes_b : 0);
+    hipError_t e = hipMalloc(&b->mem, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return fail(LAGP_E_NOMEM, "batch workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    char* q = b->mem + P.total;
+    if (P.uneven) b->order = (int32_t*)(b->mem + P.knn_b + P.cand_b + P.design_b);
+    if (n_per) { b->n_per = (int32_t*)q; q += sizes_b; }
+    if (ncand_per) { b->ncand_per = (int32_t*)q; q += sizes_b; }
+    e = hipSuccess;
+    if (P.uneven) e = hipMemcpy(b->order, P.order.data(), T * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_per) e = hipMemcpy(b->n_per, n_per, T * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ncand_per)
+        e = hipMemcpy(b->ncand_per, ncand_per, T * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) { lagp_batch_destroy(b); return hip_fail("batch set-up", e); }
+    rc = prepare_plan(design, P);
+    if (rc) { lagp_batch_destroy(b); return rc; }
+    *out = b;
+    return LAGP_OK;
+}
+
+void lagp_batch_destroy(lagp_batch* b)
+{
+    if (!b) return;
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+}
+
+int lagp_batch_info(const lagp_batch* b, int32_t* buckets, size_t* workspace_bytes)
+{
+    if (!b) return fail(LAGP_E_INVAL, "batch is NULL");
+    if (buckets) {
+        int32_t n = 0;
+        for (const Chunk& c : b->plan.chunks) n += (int32_t)c.buckets.size();
+        *buckets = n;
+    }
+    if (workspace_bytes) *workspace_bytes = b->plan.total;
+    return LAGP_OK;
+}
+
+static int batch_args(const lagp_batch* b, const double* XX, const Outputs& o)
+{
+    if (!b) return fail(LAGP_E_INVAL, "batch is NULL");
+    if (!XX || !is_device_ptr(XX)) return fail(LAGP_E_INVAL, "XX must be a device pointer");
+    if ((o.sel != nullptr) != b->have_sel) return fail(LAGP_E_INVAL, "sel must be given exactly when the batch was created with LAGP_BATCH_SEL");
+    if ((o.status != nullptr) != b->have_status)
+        return fail(LAGP_E_INVAL, "status must be given exactly when the batch was created with LAGP_BATCH_STATUS");
+    int rc = check_device(b->design);
+    if (rc) return rc;
+    return check_outputs(o, b->plan.nmax);
+}
+
+int lagp_batch_enqueue(lagp_batch* b, const double* XX, double* mean, double* s2, int32_t* df, double* var,
+                       int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+{
+    const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
+    int rc = batch_args(b, XX, o);
+    if (rc) return rc;
+    return enqueue_plan(b->design, b->plan, b->mem, b->order, b->n_per, b->ncand_per, XX, o, (hipStream_t)stream,
+                        true);
+}
+
+int lagp_batch_launch_graph(lagp_batch* b, const double* XX, double* mean, double* s2, int32_t* df, double* var,
+                            int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+{
+    const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
+    int rc = batch_args(b, XX, o);
+    if (rc) return rc;
+    const void* key[8] = {XX, mean, s2, df, var, sel, (const void*)(intptr_t)sel_stride, status};
+    if (!b->exec || memcmp(key, b->key, sizeof key) != 0) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail("hipStreamBeginCapture", e);
+        rc = enqueue_plan(b->design, b->plan, b->mem, b->order, b->n_per, b->ncand_per, XX, o, b->cap, true);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return hip_fail("hipStreamEndCapture", e);
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { b->exec = nullptr; return hip_fail("hipGraphInstantiate", e); }
+        memcpy(b->key, key, sizeof key);
+    }
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail("hipGraphLaunch", e);
+    return LAGP_OK;
+}
+
+int lagp_design_set_variant(lagp_design* d, int32_t threads, int32_t coords)
+{
+    if (!d) return fail(LAGP_E_INVAL, "design is NULL");
+    if (threads != 0 && threads != 256 && threads != 512) return fail(LAGP_E_INVAL, "threads must be 0, 256 or 512");
+    if (coords < -1 || coords > 1) return fail(LAGP_E_INVAL, "coords must be -1, 0 or 1");
+    d->force_threads = threads;
+    d->force_coords = coords;
     return LAGP_OK;
 }
 
@@ -507,8 +824,10 @@ int lagp_predict_designs(const lagp_design* design, const double* XX, int64_t T,
     if (nmax < 1) return fail(LAGP_E_INVAL, "n must be >= 1");
     if (sel_stride < nmax) return fail(LAGP_E_INVAL, "sel_stride must be >= n");
     std::string err;
-    int r = lagp::predict_run(design->dev, XX, T, sel, sel_stride, n_per, nmax, dlen, g, mean, s2, df, var, status,
-                              design->max_lds, s, &err);
+    int r = lagp::predict_prepare(nmax, design->max_lds, &err);
+    if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    r = lagp::predict_run(design->dev, XX, T, sel, sel_stride, n_per, nmax, dlen, g, mean, s2, df, var, status,
+                          design->max_lds, s, &err);
     if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     return LAGP_OK;
 }
@@ -525,7 +844,7 @@ int lagp_phase_times(lagp_design* d, double* knn_ms, double* design_ms, int64_t*
     if (!d) return fail(LAGP_E_INVAL, "design is NULL");
     double a = 0.0, b = 0.0;
     int64_t n = 0;
-    for (size_t k = 0; k + 2 < d->ev.size() + 0; k += 3) {
+    for (size_t k = 0; k + 2 < d->ev.size(); k += 3) {
         hipError_t e = hipEventSynchronize(d->ev[k + 2]);
         if (e != hipSuccess) return hip_fail("hipEventSynchronize", e);
         float x = 0.f, y = 0.f;
@@ -534,10 +853,11 @@ int lagp_phase_times(lagp_design* d, double* knn_ms, double* design_ms, int64_t*
             return fail(LAGP_E_HIP, "hipEventElapsedTime failed");
         a += x;
         b += y;
-        ++n;
+        n += d->ev_launches[k / 3];
     }
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
     d->ev.clear();
+    d->ev_launches.clear();
     if (knn_ms) *knn_ms = a;
     if (design_ms) *design_ms = b;
     if (launches) *launches = n;

@@ -11,6 +11,18 @@ namespace lagp {
 
 // Device-resident design: coordinate-major copy for streaming scans and a
 // row-major copy for gathers of single rows.
+// Raise a kernel's dynamic-LDS limit to what the device allows next to the
+// kernel's static LDS.  The limit is the device's rather than one launch's, so
+// that every launch of the kernel (eager or in a captured graph) fits.
+inline bool set_lds_limit(const void* kernel, size_t max_lds)
+{
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return false;
+    if (fa.sharedSizeBytes >= max_lds) return false;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(max_lds - fa.sharedSizeBytes)) == hipSuccess;
+}
+
 struct DeviceDesign {
     const double* Xsoa = nullptr;  // p x N
     const double* Xaos = nullptr;  // N x p
@@ -41,7 +53,10 @@ size_t knn_workspace_bytes(int64_t T, int32_t bucket_max);
 // nearest design rows, unordered unless `sorted` (uniform M only).
 int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const int32_t* M_per,
             int32_t* idx, int64_t idx_stride, bool sorted, void* ws, size_t ws_bytes, hipStream_t stream,
-            int num_cu, size_t max_lds, std::string* err);
+            int num_cu, size_t max_lds, std::string* err, bool graph_safe = false);
+// Host-side set-up of the kNN kernels for dimension p (dynamic LDS limits).
+int knn_prepare(int p, size_t max_lds, std::string* err);
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 // ---- greedy local design + prediction (design.hip)
 struct DesignLaunch {
@@ -55,6 +70,8 @@ struct DesignLaunch {
     int32_t n0 = 0, n = 0, M = 0;  // uniform values (maxima when per-location arrays are given)
     double theta = 1.0, eta = 0.0;
     int32_t precision = 0;
+    const int32_t* order = nullptr;   // work item -> location (nullable: identity over T)
+    const uint32_t* count = nullptr;  // device-side item count (nullable: T items)
     // outputs
     double* mean = nullptr;
     double* s2 = nullptr;
@@ -66,7 +83,9 @@ struct DesignLaunch {
 };
 
 struct DesignPlan {
-    int threads = 0;       // workgroup size
+    int threads = 0;       // workgroup size (input: 256 or 512 preferred)
+    int coords_pref = -1;  // input: -1 traffic model, 0 coordinates in global memory, 1 in LDS when they fit
+    int p = 0;
     int cpt = 0;           // candidate slots per thread
     int rreg = 0;          // register-resident tile rows
     int rlds = 0;          // LDS-resident tile rows
@@ -74,6 +93,7 @@ struct DesignPlan {
     bool coords_lds = false;
     int blocks = 0;        // persistent grid size
     size_t lds_bytes = 0;
+    size_t lds_limit = 0;  // device LDS per workgroup
     size_t scratch_per_block = 0;  // bytes of global scratch per block
     size_t counter_bytes = 0;
     long long global_row_reads = 0;  // modelled candidate-row reads from global memory per location
@@ -83,11 +103,17 @@ struct DesignPlan {
 int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
                 int num_cu, size_t max_lds, DesignPlan* plan, std::string* err);
 size_t design_workspace_bytes(const DesignPlan& plan);
+// Host-side set-up of the plan's kernel variant (dynamic LDS limit); call
+// before design_run, outside any stream capture.
+int design_prepare(const DesignPlan& plan, std::string* err);
+// Enqueues the persistent design kernel (a fill kernel resets its work
+// counter first); no allocation, no host synchronisation.
 int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& plan, void* ws,
                size_t ws_bytes, hipStream_t stream, std::string* err);
 
 // ---- prediction from given local designs (predict.hip)
 size_t predict_lds_bytes(int nmax);
+int predict_prepare(int32_t nmax, size_t max_lds, std::string* err);
 int predict_run(const DeviceDesign& D, const double* XX, int64_t T, const int32_t* sel, int64_t sel_stride,
                 const int32_t* n_per, int32_t nmax, double theta, double eta, double* mean, double* s2,
                 int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream, std::string* err);

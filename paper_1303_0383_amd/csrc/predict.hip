@@ -146,6 +146,17 @@ size_t predict_lds_bytes(int nmax)
     return ((size_t)nmax * (nmax + 1) / 2 + 2 * (size_t)nmax) * sizeof(double);
 }
 
+int predict_prepare(int32_t nmax, size_t max_lds, std::string* err)
+{
+    const size_t lds = predict_lds_bytes(nmax);
+    if (lds > max_lds) { *err = "local design too large for the prediction kernel"; return -1; }
+    if (!set_lds_limit((const void*)local_predict_kernel, max_lds)) {
+        *err = "cannot reserve LDS for the prediction kernel";
+        return -2;
+    }
+    return 0;
+}
+
 int predict_run(const DeviceDesign& D, const double* XX, int64_t T, const int32_t* sel, int64_t sel_stride,
                 const int32_t* n_per, int32_t nmax, double theta, double eta, double* mean, double* s2,
                 int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream, std::string* err)
@@ -153,12 +164,6 @@ int predict_run(const DeviceDesign& D, const double* XX, int64_t T, const int32_
     if (T == 0) return 0;
     const size_t lds = predict_lds_bytes(nmax);
     if (lds > max_lds) { *err = "local design too large for the prediction kernel"; return -1; }
-    if (lds > 65536 &&
-        hipFuncSetAttribute((const void*)local_predict_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess) {
-        *err = "cannot reserve LDS for the prediction kernel";
-        return -2;
-    }
     hipLaunchKernelGGL(local_predict_kernel, dim3((unsigned)T), dim3(PT), lds, stream, D.Xaos, D.y, D.p, XX, T, D.N, sel,
                        sel_stride, n_per, nmax, theta, eta, mean, s2, df, var, status);
     if (hipGetLastError() != hipSuccess) { *err = "prediction kernel launch failed"; return -2; }
