@@ -81,6 +81,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--cpu-sample", type=int, default=2048, help="locations in the CPU oracle sample (0: skip)")
     ap.add_argument("--parity-sample", type=int, default=64, help="sampled locations checked against the oracle")
+    ap.add_argument("--graph", default="auto", choices=["auto", "on", "off"],
+                    help="run each step as one HIP-graph launch of a fixed-shape batch (auto: for uneven sizes)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -121,14 +123,27 @@ def main() -> int:
                           sel=torch.empty((T, nmax), dtype=torch.int32, device=dev),
                           status=torch.empty(T, dtype=torch.int8, device=dev))
 
-    def step():
+    use_graph = args.graph == "on" or (args.graph == "auto" and w.n_per is not None)
+
+    def eager_step():
         D.predict(XX, w.n0, nmax, Mmax, w.d, w.g, n_per=n_per, ncand_per=M_per, precision=prec, out=out)
+
+    if use_graph:
+        # The batch plan (buckets, work lists, kernel variants, workspace) is
+        # made once, outside the timed region; each step is one graph launch.
+        B = lagp.Batch(D, T, w.n0, nmax, Mmax, w.d, w.g, n_per=w.n_per, ncand_per=w.ncand_per, precision=prec)
+
+        def step():
+            B.run(XX, out=out, graph=True)
+    else:
+        step = eager_step
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    lagp.lagp_timing_enable(D.handle, True)
-    lagp.lagp_phase_times(D.handle)
+    if not use_graph:
+        lagp.lagp_timing_enable(D.handle, True)
+        lagp.lagp_phase_times(D.handle)
     step_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -139,8 +154,20 @@ def main() -> int:
         step_ms.append(1e3 * (time.perf_counter() - ts))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
-    lagp.lagp_timing_enable(D.handle, False)
+    if use_graph:
+        # Per-phase device time from one eager pass with HIP events on the
+        # launch stream (graph launches carry no events inside).
+        lagp.lagp_timing_enable(D.handle, True)
+        lagp.lagp_phase_times(D.handle)
+        eager_step()
+        torch.cuda.synchronize()
+        knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+        lagp.lagp_timing_enable(D.handle, False)
+        knn_ms, des_ms = knn_ms * args.steps, des_ms * args.steps
+        launches *= args.steps
+    else:
+        knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+        lagp.lagp_timing_enable(D.handle, False)
 
     value = T * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
@@ -153,15 +180,15 @@ def main() -> int:
     else:
         flops = T * design_flops(w.n, w.ncand, w.p, w.n0)
         exps = T * design_exps(w.n, w.ncand)
-    chunks = max(1, -(-T // (1 << 17)))
-    per_launch_flops = flops / chunks
+    launches_per_step = max(1, launches // args.steps)
+    per_launch_flops = flops / launches_per_step
     avg_launch_s = des_ms / max(launches, 1) / 1e3
     achieved = per_launch_flops / avg_launch_s / 1e12
     roofline = {"kernel": "design_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
-                "flops_per_launch": per_launch_flops, "exps_per_launch": exps / chunks,
-                "exp_rate_G_per_s": round(exps / chunks / avg_launch_s / 1e9, 2)}
+                "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": launches_per_step,
+                "flops_per_launch": per_launch_flops, "exps_per_launch": exps / launches_per_step,
+                "exp_rate_G_per_s": round(exps / launches_per_step / avg_launch_s / 1e9, 2)}
     traffic_file = os.path.join(ROOT, "profiles", f"design_kernel_{args.workload}_traffic.txt")
     if os.path.exists(traffic_file) and args.precision == "fp64":
         for line in open(traffic_file):
@@ -174,7 +201,7 @@ def main() -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32-tile", "data": "synthetic",
         "config": {"workload": args.workload, "N": w.N, "p": w.p, "T": T, "n0": w.n0, "n": nmax,
-                   "ncand": Mmax, "d": w.d, "g": w.g, "uneven": w.n_per is not None},
+                   "ncand": Mmax, "d": w.d, "g": w.g, "uneven": w.n_per is not None, "graph": use_graph},
         "phase_ms_per_step": {"knn": round(knn_ms / args.steps, 3), "design": round(des_ms / args.steps, 3)},
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),

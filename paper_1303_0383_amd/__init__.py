@@ -25,6 +25,10 @@ LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32 = 0, 1
 LAGP_PTR_HOST, LAGP_STRICT = 1, 2
 LAGP_BATCH_SEL, LAGP_BATCH_STATUS = 1, 2
 
+# torch first: its bundled HIP runtime is then the one the library binds to.
+# Loading the library first would map a second HIP runtime into the process.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                       "(python -m paper_1303_0383_amd.build)")

@@ -4,12 +4,14 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblagp.so")
-SOURCES = ["lagp_api.cpp", "knn.hip", "design.hip", "predict.hip"]
+SOURCES = ["lagp_api.cpp", "knn.hip", "design.hip", "design_f64.hip", "design_f64_trim.hip", "design_mix.hip",
+           "design_mix_trim.hip", "predict.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -24,18 +26,25 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + FLAGS + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC] + FLAGS + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # Translation units compile in parallel (the kernel variants dominate).
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)

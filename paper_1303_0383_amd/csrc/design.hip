@@ -1,612 +1,19 @@
-// design.hip -- greedy ALC local design and local GP prediction on gfx950.
-//
-// One 256-thread workgroup owns one predictive location at a time and pulls
-// the next location from a work counter (persistent kernel, Section 4.1's
-// independent loop over locations).  Thread `tid` owns the candidate slots
-// tid + k * 256, k < CPT.
-//
-// Algebra.  Write L_j for the Cholesky factor of K_j = K(X_j, X_j) + g I and
-// keep the whitened tile W_j = L_j^{-1} K(X_j, C) over all candidates C, with
-// w_x = L_j^{-1} k_j(x) and u = L_j^{-1} Y_j.  Then for every candidate c
-//   v_j(c)     = 1 + g - ||W_j[:,c]||^2,
-//   cov_j(x,c) = K(x,c) - w_x . W_j[:,c],
-//   ALC_j(c)   = cov_j(x,c)^2 / v_j(c)            (eqs dxy / dxy2),
-// and adding the chosen s appends one row to each of them:
-//   delta = sqrt(v_j(s)),
-//   r_c   = (K(s,c) - W_j[:,s] . W_j[:,c]) / delta  (row j of W),
-//   r_x   = (K(s,x) - W_j[:,s] . w_x) / delta,  r_y = (y_s - W_j[:,s] . u) / delta,
-//   v_{j+1}(c) = v_j(c) - r_c^2,  cov_{j+1}(x,c) = cov_j(x,c) - r_x r_c.
-// This is the partitioned-inverse step of SM Section 1 written for the factor
-// (the new last row of L_{j+1}^{-1} is [-(l/delta)' L_j^{-1}, 1/delta] with
-// l = L_j^{-1} k_j(s)), carried to every candidate at once.  The chosen
-// columns of W are the rows of L_n, so the final prediction
-//   mean = w_x . u,  psi = u . u,  v_n(x) = 1 + g - w_x . w_x  (eqs predgp, preds2)
-// needs no refactorisation.  Every dot product runs in ascending index
-// order with separate multiply and subtract (the file is compiled with
-// -ffp-contract=off), the same operation order as a row-by-row Cholesky
-// factorisation and forward substitution.
-//
-// Storage of W (rows in selection order): the first RREG rows in registers
-// (compile time), the next `rlds` rows in LDS, the rest in a per-workgroup
-// global scratch slab.  Candidate coordinates live in LDS when they fit,
-// else in the same slab.
+// design.hip -- plan and launch of the greedy-design kernel (the kernel
+// itself is in design_kernel.h): tile-row placement across registers, LDS and
+// global memory from a traffic model, workspace sizing, and dispatch to the
+// compiled variant.
 #include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdint.h>
 
 #include <algorithm>
 
-#include "lagp_internal.h"
+#include "design_kernel.h"
 
 namespace lagp {
 
-
-struct DesignArgs {
-    const double* Xaos;
-    const double* y;
-    int p;
-    const double* XX;
-    int64_t T;
-    const int32_t* cand;
-    int64_t cand_stride;
-    const int32_t* n_per;
-    const int32_t* M_per;
-    int n0, n, M;
-    double theta, eta;
-    double* mean;
-    double* s2;
-    int32_t* df;
-    double* var;
-    int32_t* sel;
-    int64_t sel_stride;
-    int8_t* status;
-    double* scratch;
-    int64_t scratch_stride;  // doubles per workgroup
-    int rlds, coords_lds;
-    int nmax;
-    unsigned int* counter;
-    const int32_t* order;    // nullable: work item -> location (else identity)
-    const uint32_t* count;   // nullable: number of work items, read on the device (else T)
-};
-
-// ---- exact division helpers
-// a / b correctly rounded from y = RN(1/b): q = RN(a*y), r = a - q*b (exact
-// through the fused multiply-add), RN(q + r*y) = RN(a/b) (Markstein's
-// correction; inputs here are normal and finite).
-__device__ __forceinline__ double div_by(double a, double b, double y)
+static int launch_any(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    const double q = a * y;
-    const double r = __builtin_fma(-q, b, a);
-    return __builtin_fma(r, y, q);
-}
-
-// ---- wave reductions with DPP (xor 1, xor 2 as quad permutes; rotations by
-// 4 and 8 inside each 16-lane row), then cross-row shuffles.
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
-    const int hi = dpp_i<CTRL>((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Candidate ordering for the argmax: larger score first, then smaller index.
-__device__ __forceinline__ bool better(double a, int ia, double b, int ib)
-{
-    return a > b || (a == b && ia < ib);
-}
-// Nearest-neighbour ordering: smaller squared distance first, then smaller index.
-__device__ __forceinline__ bool nearer(double a, int ia, double b, int ib)
-{
-    return a < b || (a == b && ia < ib);
-}
-
-// Four consecutive LDS doubles (16-byte aligned start) as two 16-byte reads.
-__device__ __forceinline__ void ld4(const double* p, double* o)
-{
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
-}
-
-template <int P>
-__device__ __forceinline__ double sqdist_lds(const double* __restrict__ a, const double* __restrict__ c,
-                                             int cstride, int p)
-{
-    // a: uniform point (LDS/registers); c: candidate coordinates with stride cstride.
-    double s = 0.0;
-    if (P > 0) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            double t = a[k] - c[k * cstride];
-            s += t * t;
-        }
-    } else {
-        for (int k = 0; k < p; ++k) {
-            double t = a[k] - c[k * cstride];
-            s += t * t;
-        }
-    }
-    return s;
-}
-
-// Rows of the whitened tile kept in registers for a workgroup size and slot
-// count.  With 256 threads (one wave per SIMD) a lane can hold 512 registers,
-// the upper half as accumulation registers the compiler uses as spill space;
-// with 512 threads a lane has 256.
-__host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = false)
-{
-    return mix ? (dt == 256 ? (cpt >= 8 ? 8 : cpt == 4 ? (cl ? 24 : 16) : cpt == 2 ? 48 : 64)
-                            : (cpt >= 4 ? 0 : cpt == 2 ? 8 : 32))
-               : (dt == 256 ? (cpt >= 16 ? 0 : cpt == 8 ? 4 : cpt == 4 ? (cl ? 16 : 12) : cpt == 2 ? 32 : 64)
-                            : (cpt >= 4 ? 0 : cpt == 2 ? 4 : 16));
-}
-
-// Rows per prefetch block of the global part of the tile (two blocks are in
-// flight).
-__host__ __device__ constexpr int prefetch_rows(int cpt)
-{
-    return cpt >= 4 ? 2 : 8 / cpt;
-}
-
-// Combine (value, design index, slot) with a partner lane's triple.
-// MAX: larger value wins (argmax of ALC); otherwise smaller wins (nearest).
-template <bool MAX>
-__device__ __forceinline__ void pick(double& v, int& i, int& s, double ov, int oi, int os)
-{
-    const bool take = os >= 0 && (s < 0 || (MAX ? better(ov, oi, v, i) : nearer(ov, oi, v, i)));
-    if (take) { v = ov; i = oi; s = os; }
-}
-
-template <bool MAX>
-__device__ __forceinline__ void wave_pick(double& v, int& i, int& s)
-{
-    pick<MAX>(v, i, s, dpp_d<0xB1>(v), dpp_i<0xB1>(i), dpp_i<0xB1>(s));     // xor 1
-    pick<MAX>(v, i, s, dpp_d<0x4E>(v), dpp_i<0x4E>(i), dpp_i<0x4E>(s));     // xor 2
-    pick<MAX>(v, i, s, dpp_d<0x124>(v), dpp_i<0x124>(i), dpp_i<0x124>(s));  // rotate 4 in row
-    pick<MAX>(v, i, s, dpp_d<0x128>(v), dpp_i<0x128>(i), dpp_i<0x128>(s));  // rotate 8 in row
-    pick<MAX>(v, i, s, __shfl_xor(v, 16), __shfl_xor(i, 16), __shfl_xor(s, 16));
-    pick<MAX>(v, i, s, __shfl_xor(v, 32), __shfl_xor(i, 32), __shfl_xor(s, 32));
-}
-
-// Four consecutive LDS floats (16-byte aligned start).
-__device__ __forceinline__ void ld4(const float* p, float* o)
-{
-    const float4 a = *reinterpret_cast<const float4*>(p);
-    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
-}
-
-// DT threads per workgroup, CPT candidate slots per thread, RREG register
-// rows, P compile-time dimension (0: runtime), CL candidate coordinates in LDS,
-// MIX: the whitened tile stored and contracted in FP32 (ranking only).
-template <int DT, int CPT, int RREG, int P, bool CL, bool MIX>
-__global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
-{
-    using TW = typename std::conditional<MIX, float, double>::type;
-    constexpr int DWAVES = DT / 64;
-    extern __shared__ double smem[];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int p = P > 0 ? P : A.p;
-    const int nmax = (A.nmax + 3) & ~3;   // padded: 4-row blocks read up to 3 entries ahead
-    const int Mpad = CPT * DT;
-    const double theta = A.theta, eta = A.eta;
-    const double one_eta = 1.0 + eta;
-    const double rtheta = 1.0 / theta;
-
-    // ---- LDS carve-up (doubles first, then ints)
-    TW* ws = (TW*)smem;              // [nmax] column of the chosen candidate
-    TW* wx = (TW*)(smem + nmax);     // [nmax] L^{-1} k(x)
-    double* uu = smem + 2 * nmax;    // [nmax] L^{-1} Y
-    double* xl = uu + nmax;          // [p]    predictive location
-    double* xsl = xl + p;            // [p+1]  (spare)
-    double* misc = xsl + p + 1;      // [4]    v_s
-    double* redv = misc + 4;         // [2*DWAVES] per-wave best scores
-    int* redi = (int*)(redv + 2 * DWAVES);  // [2*DWAVES] best design index
-    int* reds = redi + 2 * DWAVES;          // [2*DWAVES] best slot
-    int* forced = reds + 2 * DWAVES;        // [nmax] slots of the nearest neighbours
-    int* ctl = forced + nmax;               // [4]  location
-    size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
-    off = (off + 15) & ~(size_t)15;
-    double* Xcl = (double*)((char*)smem + off);              // [p+1][Mpad] when CL: coordinates, y
-    TW* Wl = (TW*)(Xcl + (CL ? (size_t)(p + 1) * Mpad : 0));  // [rlds][Mpad]
-
-    double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-    TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)(p + 1) * Mpad));
-    double* Xc = CL ? Xcl : Xcg;
-    const int rlds = A.rlds;
-    const int G0 = RREG + rlds;   // first global row
-    for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = 0.0;
-    (void)xsl;
-
-    for (;;) {
-        if (tid == 0) ctl[0] = (int)atomicAdd(A.counter, 1u);
-        __syncthreads();
-        const int64_t w = ctl[0];
-        if (w >= (A.count ? (int64_t)*A.count : A.T)) break;
-        const int64_t t = A.order ? A.order[w] : w;
-        const int n = A.n_per ? A.n_per[t] : A.n;
-        const int M = A.M_per ? A.M_per[t] : A.M;
-        const int n0 = A.n0;
-        const int32_t* cand = A.cand + t * A.cand_stride;
-        for (int k = tid; k < p; k += DT) xl[k] = A.XX[t * p + k];
-        // ws, wx, uu are zero beyond the current step: padded terms subtract an exact 0.
-        for (int l = tid; l < nmax; l += DT) { ws[l] = 0.0; wx[l] = 0.0; uu[l] = 0.0; }
-        if (A.sel)
-            for (int i = tid; i < n; i += DT) A.sel[t * A.sel_stride + i] = -1;
-        __syncthreads();
-        double xr[P > 0 ? P : 1];
-        if (P > 0) {
-#pragma unroll
-            for (int k = 0; k < (P > 0 ? P : 1); ++k) xr[k] = xl[k];
-        }
-        const double* xp = P > 0 ? xr : xl;
-
-        // ---- gather candidates (coordinates and y into the coordinate block);
-        //      K(x,c) and v_0(c) = 1 + g
-        int ci[CPT];
-        double v[CPT], cov[CPT], d2[CPT];
-        TW Wr[RREG > 0 ? RREG : 1][CPT];
-#pragma unroll
-        for (int l = 0; l < (RREG > 0 ? RREG : 1); ++l)
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) Wr[l][k] = 0.0;
-        uint32_t chosen = 0;   // bit k: slot retired (chosen or absent)
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int slot = tid + k * DT;
-            if (slot < M) {
-                const int c = cand[slot];
-                ci[k] = c;
-                Xc[(int64_t)p * Mpad + slot] = A.y[c];
-                const double* xc = A.Xaos + (int64_t)c * p;
-                double sq = 0.0;
-                for (int kk = 0; kk < p; ++kk) {
-                    const double ck = xc[kk];
-                    Xc[(int64_t)kk * Mpad + slot] = ck;
-                    const double tt = xp[kk] - ck;
-                    sq += tt * tt;
-                }
-                d2[k] = sq;
-                cov[k] = exp(-div_by(sq, theta, rtheta));
-                v[k] = one_eta;
-            } else {
-                ci[k] = 0x7fffffff;
-                Xc[(int64_t)p * Mpad + slot] = 0.0;
-                d2[k] = INFINITY;
-                cov[k] = 0.0;
-                v[k] = one_eta;
-                chosen |= 1u << k;
-                for (int kk = 0; kk < p; ++kk) Xc[(int64_t)kk * Mpad + slot] = 0.0;
-            }
-        }
-
-        // ---- starting design: the n0 nearest candidates, by (distance, index)
-        {
-            uint32_t taken = chosen;
-            for (int r = 0; r < n0; ++r) {
-                double bd = INFINITY;
-                int bi = 0x7fffffff, bs = -1;
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) {
-                    if (!((taken >> k) & 1u) && nearer(d2[k], ci[k], bd, bi)) {
-                        bd = d2[k]; bi = ci[k]; bs = tid + k * DT;
-                    }
-                }
-                wave_pick<false>(bd, bi, bs);
-                const int par = (r & 1) * DWAVES;
-                if (lane == 0) { redv[par + wave] = bd; redi[par + wave] = bi; reds[par + wave] = bs; }
-                __syncthreads();
-                bd = redv[par]; bi = redi[par]; bs = reds[par];
-                for (int w = 1; w < DWAVES; ++w) pick<false>(bd, bi, bs, redv[par + w], redi[par + w], reds[par + w]);
-                if (tid == 0) forced[r] = bs;
-                if (bs >= 0 && (bs % DT) == tid) taken |= 1u << (bs / DT);
-            }
-        }
-        __syncthreads();
-
-        // ---- greedy steps
-        int s_next = -1;
-        int notpd = 0;
-        for (int i = 0; i < n; ++i) {
-            const int s = (i < n0) ? forced[i] : s_next;
-            if (s < 0 || s >= M) { notpd = 1; break; }
-            const int s_lane = s % DT;
-            const int s_k = s / DT;
-            // Phase A (before the barrier): the owner publishes the register
-            // part of its column and v(s); everyone copies the LDS / global
-            // part and evaluates K(s, .) for x and its own candidates.
-            if (tid == s_lane) {
-                const int kk = __builtin_amdgcn_readfirstlane(s_k);
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) {
-                    if (k == kk) {
-#pragma unroll
-                        for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
-                            if (l < i) ws[l] = Wr[l][k];
-                        misc[0] = v[k];
-                        ctl[1] = ci[k];
-                    }
-                }
-                chosen |= 1u << kk;
-            }
-            for (int l = RREG + tid; l < i; l += DT)
-                ws[l] = (l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s];
-            double xs[P > 0 ? P : 1];
-            if (P > 0) {
-#pragma unroll
-                for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
-            }
-            const double ys = Xc[(int64_t)p * Mpad + s];
-            const double* xsp = P > 0 ? xs : xl;   // runtime dimension: read below from Xc
-            double ax, acc[CPT];
-            if (P > 0) {
-                ax = exp(-div_by(sqdist_lds<P>(xsp, xl, 1, p), theta, rtheta));
-#pragma unroll
-                for (int k = 0; k < CPT; ++k)
-                    acc[k] = exp(-div_by(sqdist_lds<P>(xsp, Xc + tid + k * DT, Mpad, p), theta, rtheta));
-            } else {
-                double sqx = 0.0, sq[CPT];
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) sq[k] = 0.0;
-                for (int kk = 0; kk < p; ++kk) {
-                    const double a = Xc[(int64_t)kk * Mpad + s];
-                    const double tx = a - xl[kk];
-                    sqx += tx * tx;
-#pragma unroll
-                    for (int k = 0; k < CPT; ++k) {
-                        const double tc = a - Xc[(int64_t)kk * Mpad + tid + k * DT];
-                        sq[k] += tc * tc;
-                    }
-                }
-                ax = exp(-div_by(sqx, theta, rtheta));
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) acc[k] = exp(-div_by(sq[k], theta, rtheta));
-            }
-            (void)xsp;
-
-            // Prefetch the first global rows.
-            constexpr int U = prefetch_rows(CPT);
-            TW pre[U][CPT];
-            float dot[CPT], dotx = 0.0f;   // FP32 contraction (MIX)
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) dot[k] = 0.0f;
-            const int gcount = i > G0 ? i - G0 : 0;
-            if (gcount > 0) {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (u < gcount) {
-                        const TW* row = Wg + (int64_t)u * Mpad + tid;
-#pragma unroll
-                        for (int k = 0; k < CPT; ++k) pre[u][k] = row[k * DT];
-                    }
-            }
-            __syncthreads();   // B1: column of s and v(s) published
-
-            const double vs = misc[0];
-            if (!(vs > 0.0)) { notpd = 1; break; }
-            const double delta = sqrt(vs);
-            const double rdelta = 1.0 / delta;
-            double ay = ys;
-            if (i == n - 1) {
-                for (int l = 0; l < i; ++l) {
-                    const double w = ws[l];
-                    ax -= w * (double)wx[l];
-                    ay -= w * uu[l];
-                }
-                if (tid == 0) {
-                    wx[i] = div_by(ax, delta, rdelta);
-                    uu[i] = div_by(ay, delta, rdelta);
-                    if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
-                }
-                break;
-            }
-
-            // Row i of W for every live candidate: acc = K(s,c) - sum_l ws[l] W[l][c].
-            // Register rows, four per block; rows >= i within a block are zero.
-#pragma unroll
-            for (int l0 = 0; l0 < (RREG > 0 ? RREG : 0); l0 += 4) {
-                if (l0 < i) {
-                    TW w[4], xv[4];
-                    ld4(ws + l0, w);
-                    ld4(wx + l0, xv);
-                    if constexpr (MIX) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(w[r], Wr[l0 + r][k], dot[k]);
-                            dotx = __builtin_fmaf(w[r], xv[r], dotx);
-                        }
-                    } else {
-                        double uv[4];
-                        ld4(uu + l0, uv);
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) acc[k] -= w[r] * Wr[l0 + r][k];
-                            ax -= w[r] * xv[r];
-                            ay -= w[r] * uv[r];
-                        }
-                    }
-                }
-            }
-            {
-                // LDS rows [RREG, min(i, G0)), four per block.  A block may run
-                // past i (or past G0 into rows that are never written): the
-                // weight is zero there and the LDS rows hold finite values, so
-                // those terms subtract an exact 0.
-                const int le = i < G0 ? i : G0;
-                constexpr int QB = CPT >= 8 ? 1 : CPT == 4 ? 2 : 4;   // rows loaded ahead
-#pragma unroll 2
-                for (int l0 = RREG; l0 < le; l0 += 4) {
-                    TW w[4], xv[4];
-                    double uv[4];
-                    ld4(ws + l0, w);
-                    ld4(wx + l0, xv);
-                    if constexpr (!MIX) ld4(uu + l0, uv);
-#pragma unroll
-                    for (int r0 = 0; r0 < 4; r0 += QB) {
-                        TW q[QB][CPT];
-#pragma unroll
-                        for (int r = 0; r < QB; ++r) {
-                            const int lr = (l0 + r0 + r < G0) ? l0 + r0 + r : l0;   // stay inside the LDS tile
-                            const TW* row = Wl + (int64_t)(lr - RREG) * Mpad + tid;
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) q[r][k] = row[k * DT];
-                        }
-#pragma unroll
-                        for (int r = 0; r < QB; ++r) {
-                            const TW wr = (l0 + r0 + r < le) ? w[r0 + r] : (TW)0;
-                            if constexpr (MIX) {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wr, q[r][k], dot[k]);
-                                dotx = __builtin_fmaf(wr, xv[r0 + r], dotx);
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) acc[k] -= wr * q[r][k];
-                                ax -= wr * xv[r0 + r];
-                                ay -= wr * uv[r0 + r];
-                            }
-                        }
-                    }
-                }
-            }
-            if (gcount > 0) {
-                // Global rows in blocks of U, the next block loaded before the
-                // current one is consumed.  Per-candidate order stays ascending.
-                int l = G0;
-                while (l < i) {
-                    const int nb = (i - l) < U ? (i - l) : U;     // rows in pre[]
-                    const int l2 = l + nb;
-                    const int nb2 = (i - l2) < U ? (i - l2) : U;   // rows of the next block
-                    TW nxt[U][CPT];
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (u < nb2) {
-                            const TW* row = Wg + (int64_t)(l2 + u - G0) * Mpad + tid;
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) nxt[u][k] = row[k * DT];
-                        }
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (u < nb) {
-                            const TW w = ws[l + u];
-                            if constexpr (MIX) {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(w, pre[u][k], dot[k]);
-                                dotx = __builtin_fmaf(w, wx[l + u], dotx);
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) acc[k] -= w * pre[u][k];
-                                ax -= w * wx[l + u];
-                                ay -= w * uu[l + u];
-                            }
-                        }
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-#pragma unroll
-                        for (int k = 0; k < CPT; ++k) pre[u][k] = nxt[u][k];
-                    l = l2;
-                }
-            }
-            if constexpr (MIX) {
-                ax -= (double)dotx;
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) acc[k] -= (double)dot[k];
-            }
-            const double rx = MIX ? ax * rdelta : div_by(ax, delta, rdelta);
-            if (tid == 0) {
-                wx[i] = rx;
-                uu[i] = div_by(ay, delta, rdelta);
-                if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
-            }
-            double r[CPT];
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-                r[k] = MIX ? acc[k] * rdelta : div_by(acc[k], delta, rdelta);
-                v[k] -= r[k] * r[k];
-                cov[k] -= rx * r[k];
-            }
-            if (i < RREG) {
-#pragma unroll
-                for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
-                    if (l == i) {
-#pragma unroll
-                        for (int k = 0; k < CPT; ++k) Wr[l][k] = (TW)r[k];
-                    }
-            } else if (i < G0) {
-                TW* row = Wl + (int64_t)(i - RREG) * Mpad + tid;
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
-            } else {
-                TW* row = Wg + (int64_t)(i - G0) * Mpad + tid;
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
-            }
-
-            // Argmax of ALC_{i+1} over live candidates (needed from step n0 on).
-            // The score only ranks candidates, so cov^2 / v uses a refined
-            // reciprocal of v.
-            double bv = -INFINITY;
-            int bi = 0x7fffffff, bs = -1;
-            if (i + 1 >= n0) {
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) {
-                    if (!((chosen >> k) & 1u)) {
-                        double a = -INFINITY;
-                        if (v[k] > 0.0) {
-                            double y = __builtin_amdgcn_rcp(v[k]);
-                            y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
-                            a = (cov[k] * cov[k]) * y;
-                        }
-                        if (bs < 0 || better(a, ci[k], bv, bi)) { bv = a; bi = ci[k]; bs = tid + k * DT; }
-                    }
-                }
-                wave_pick<true>(bv, bi, bs);
-                if (lane == 0) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
-            }
-            __syncthreads();   // B2: partial maxima published; everyone is done with ws
-            if (i + 1 >= n0) {
-                bv = redv[0]; bi = redi[0]; bs = reds[0];
-                for (int w = 1; w < DWAVES; ++w) pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
-                if (bs < 0 || bv == -INFINITY) { notpd = 1; break; }
-                s_next = bs;
-            }
-        }
-
-        // ---- prediction (eqs predgp, preds2 with N -> n); with an FP32 tile the
-        //      prediction kernel refactorises K_n in FP64 from the indices.
-        __syncthreads();
-        if (tid == 0 && !MIX) {
-            double mean, s2v, var;
-            if (notpd) {
-                mean = s2v = var = NAN;
-            } else {
-                double m = 0.0, ps = 0.0, q = 0.0;
-                for (int l = 0; l < n; ++l) {
-                    m += wx[l] * uu[l];
-                    ps += uu[l] * uu[l];
-                    q += wx[l] * wx[l];
-                }
-                const double vxn = one_eta - q;
-                mean = m;
-                s2v = ps * vxn / n;
-                var = n > 2 ? ps * vxn / (n - 2) : NAN;
-            }
-            A.mean[t] = mean;
-            A.s2[t] = s2v;
-            if (A.var) A.var[t] = var;
-            if (A.df) A.df[t] = n;
-            if (A.status) A.status[t] = notpd ? 1 : 0;
-        }
-        __syncthreads();
-    }
+    if (plan.mix) return plan.trim ? design_launch_mix_trim(a, plan, stream, err) : design_launch_mix(a, plan, stream, err);
+    return plan.trim ? design_launch_f64_trim(a, plan, stream, err) : design_launch_f64(a, plan, stream, err);
 }
 
 // ------------------------------------------------------------------ plan
@@ -629,7 +36,7 @@ static long long global_row_reads(int nmax, int g0)
     return r;
 }
 
-int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
+int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin, int32_t n0, int32_t precision,
                 int num_cu, size_t max_lds, DesignPlan* plan, std::string* err)
 {
     (void)n0;
@@ -667,6 +74,8 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, i
     plan->threads = dt;
     plan->p = p;
     plan->lds_limit = max_lds;
+    // Trimmed variant when some location leaves a whole slot column empty.
+    plan->trim = cpt > 1 && Mmin <= (cpt - 1) * dt;
     plan->mix = mix;
     plan->rreg = cl ? rregA : rregB;
     plan->rlds = cl ? rldsA : rldsB;
@@ -685,64 +94,9 @@ size_t design_workspace_bytes(const DesignPlan& plan)
     return plan.counter_bytes + plan.scratch_per_block * (size_t)plan.blocks;
 }
 
-// With `a` null the kernel variant's dynamic-LDS limit is raised (host-side
-// set-up, kept out of stream capture); otherwise the kernel is launched.
-template <int DT, int CPT, int P, bool CL, bool MIX>
-static int launch_design(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
-{
-    constexpr int RREG = rreg_for(DT, CPT, CL, MIX);
-    auto kern = design_kernel<DT, CPT, RREG, P, CL, MIX>;
-    if (!a) {
-        // Plans of one variant may differ in LDS size and a captured graph may
-        // launch any of them: the limit is the device's.
-        if (!set_lds_limit((const void*)kern, plan.lds_limit)) {
-            *err = "cannot reserve LDS for the design kernel";
-            return -2;
-        }
-        return 0;
-    }
-    hipLaunchKernelGGL(kern, dim3(plan.blocks), dim3(DT), plan.lds_bytes, stream, *a);
-    if (hipGetLastError() != hipSuccess) { *err = "design kernel launch failed"; return -2; }
-    return 0;
-}
-
-template <int DT, int CPT, bool CL, bool MIX>
-static int launch_design_p(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
-{
-    switch (plan.p) {
-    case 2: return launch_design<DT, CPT, 2, CL, MIX>(a, plan, stream, err);
-    case 4: return launch_design<DT, CPT, 4, CL, MIX>(a, plan, stream, err);
-    case 8: return launch_design<DT, CPT, 8, CL, MIX>(a, plan, stream, err);
-    default: return launch_design<DT, CPT, 0, CL, MIX>(a, plan, stream, err);
-    }
-}
-
-template <int DT, int CPT>
-static int launch_design_c(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
-{
-    if (plan.mix)
-        return plan.coords_lds ? launch_design_p<DT, CPT, true, true>(a, plan, stream, err)
-                               : launch_design_p<DT, CPT, false, true>(a, plan, stream, err);
-    return plan.coords_lds ? launch_design_p<DT, CPT, true, false>(a, plan, stream, err)
-                           : launch_design_p<DT, CPT, false, false>(a, plan, stream, err);
-}
-
-template <int DT>
-static int launch_design_dt(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
-{
-    switch (plan.cpt) {
-    case 1: return launch_design_c<DT, 1>(a, plan, stream, err);
-    case 2: return launch_design_c<DT, 2>(a, plan, stream, err);
-    case 4: return launch_design_c<DT, 4>(a, plan, stream, err);
-    case 8: return launch_design_c<DT, 8>(a, plan, stream, err);
-    default: return launch_design_c<DT, 8>(a, plan, stream, err);
-    }
-}
-
 int design_prepare(const DesignPlan& plan, std::string* err)
 {
-    return plan.threads == 256 ? launch_design_dt<256>(nullptr, plan, nullptr, err)
-                               : launch_design_dt<512>(nullptr, plan, nullptr, err);
+    return launch_any(nullptr, plan, nullptr, err);
 }
 
 int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& plan, void* ws,
@@ -781,8 +135,7 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
     a.order = L.order;
     a.count = L.count;
     fill_u32(a.counter, 1, 0u, stream);
-    return plan.threads == 256 ? launch_design_dt<256>(&a, plan, stream, err)
-                               : launch_design_dt<512>(&a, plan, stream, err);
+    return launch_any(&a, plan, stream, err);
 }
 
 }  // namespace lagp

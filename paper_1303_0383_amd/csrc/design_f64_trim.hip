@@ -1,0 +1,12 @@
+// design_f64_trim.hip -- greedy-design kernel variants with MIX=false, TRIM=true
+// (one translation unit per pair so that the variants compile in parallel).
+#include "design_kernel.h"
+
+namespace lagp {
+
+int design_launch_f64_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+{
+    return launch_variant<false, true>(a, plan, stream, err);
+}
+
+}  // namespace lagp

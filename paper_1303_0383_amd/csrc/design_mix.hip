@@ -1,0 +1,12 @@
+// design_mix.hip -- greedy-design kernel variants with MIX=true, TRIM=false
+// (one translation unit per pair so that the variants compile in parallel).
+#include "design_kernel.h"
+
+namespace lagp {
+
+int design_launch_mix(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+{
+    return launch_variant<true, false>(a, plan, stream, err);
+}
+
+}  // namespace lagp

@@ -226,14 +226,14 @@ int lagp_knn(const lagp_design* design, const double* XX, int64_t T, int32_t M, 
 namespace {
 
 struct Bucket {
-    int32_t nmax = 0, Mmax = 0;
+    int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
     int64_t first = 0, count = 0;   // range of the chunk's work list
     lagp::DesignPlan plan;
 };
 
 struct Chunk {
     int64_t t0 = 0, T = 0;
-    int32_t nmax = 0, Mmax = 0;
+    int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
     std::vector<Bucket> buckets;
     lagp::DesignPlan redo;   // FP64 plan for locations the mixed mode could not finish
 };
@@ -313,11 +313,12 @@ void choose_variant(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, 
         }
 }
 
-int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int32_t n0, lagp::DesignPlan* plan)
+int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int32_t Mmin, int32_t n0,
+                lagp::DesignPlan* plan)
 {
     std::string err;
     choose_variant(d, prec, nmax, Mmax, plan);
-    if (lagp::design_plan(d->dev, nmax, Mmax, n0, prec, d->num_cu, d->max_lds, plan, &err))
+    if (lagp::design_plan(d->dev, nmax, Mmax, Mmin, n0, prec, d->num_cu, d->max_lds, plan, &err))
         return fail(LAGP_E_INVAL, err);
     return LAGP_OK;
 }
@@ -374,6 +375,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
             Bucket b;
             b.nmax = c.nmax = nmax;
             b.Mmax = c.Mmax = Mmax;
+            b.Mmin = c.Mmin = Mmax;
             b.first = 0;
             b.count = c.T;
             c.buckets.push_back(b);
@@ -385,6 +387,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
                 const int32_t nt = hn ? hn[t] : prm->n, mt = hm ? hm[t] : prm->ncand;
                 c.nmax = std::max(c.nmax, nt);
                 c.Mmax = std::max(c.Mmax, mt);
+                c.Mmin = std::min(c.Mmin, mt);
                 key[k] = {-((int64_t)size_class(mt, 256) << 16 | size_class(nt, 32)), k};
             }
             auto cost = [&](int64_t k) {
@@ -405,6 +408,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
                     const int64_t t = t0 + key[e].second;
                     b.nmax = std::max(b.nmax, hn ? hn[t] : prm->n);
                     b.Mmax = std::max(b.Mmax, hm ? hm[t] : prm->ncand);
+                    b.Mmin = std::min(b.Mmin, hm ? hm[t] : prm->ncand);
                     P->order[t0 + e] = (int32_t)key[e].second;
                     ++e;
                 }
@@ -415,12 +419,12 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
             }
         }
         for (Bucket& b : c.buckets) {
-            int rc = plan_design(d, prm->precision, b.nmax, b.Mmax, prm->n0, &b.plan);
+            int rc = plan_design(d, prm->precision, b.nmax, b.Mmax, b.Mmin, prm->n0, &b.plan);
             if (rc) return rc;
             design_b = std::max(design_b, lagp::design_workspace_bytes(b.plan));
         }
         if (P->mix) {
-            int rc = plan_design(d, LAGP_PREC_FP64, c.nmax, c.Mmax, prm->n0, &c.redo);
+            int rc = plan_design(d, LAGP_PREC_FP64, c.nmax, c.Mmax, c.Mmin, prm->n0, &c.redo);
             if (rc) return rc;
             design_b = std::max(design_b, lagp::design_workspace_bytes(c.redo));
         }
@@ -438,9 +442,9 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
         for (const Chunk& c : P->chunks)
             for (const Bucket& b : c.buckets)
                 fprintf(stderr,
-                        "[lagp] bucket: locations=%lld n<=%d ncand<=%d p=%d threads=%d slots/thread=%d rows: reg=%d "
+                        "[lagp] bucket: locations=%lld n<=%d ncand<=%d p=%d threads=%d slots/thread=%d trim=%d rows: reg=%d "
                         "lds=%d global=%d coords_lds=%d lds=%zu B global_row_reads/loc=%lld workspace=%zu B\n",
-                        (long long)b.count, b.nmax, b.Mmax, d->dev.p, b.plan.threads, b.plan.cpt, b.plan.rreg,
+                        (long long)b.count, b.nmax, b.Mmax, d->dev.p, b.plan.threads, b.plan.cpt, (int)b.plan.trim, b.plan.rreg,
                         b.plan.rlds, b.plan.rglob, (int)b.plan.coords_lds, b.plan.lds_bytes,
                         b.plan.global_row_reads, P->total);
     return LAGP_OK;

@@ -98,9 +98,11 @@ struct DesignPlan {
     size_t counter_bytes = 0;
     long long global_row_reads = 0;  // modelled candidate-row reads from global memory per location
     bool mix = false;                // FP32 tile
+    bool trim = false;               // variant that skips empty slot columns
 };
 
-int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t n0, int32_t precision,
+// Mmin: the smallest candidate-set size among the locations the plan will run.
+int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin, int32_t n0, int32_t precision,
                 int num_cu, size_t max_lds, DesignPlan* plan, std::string* err);
 size_t design_workspace_bytes(const DesignPlan& plan);
 // Host-side set-up of the plan's kernel variant (dynamic LDS limit); call
