@@ -76,13 +76,17 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_n50", choices=["c2_n50", "c2", "c1", "c0", "c3"])
+    ap.add_argument("--workload", default="c2_n50", choices=["c2_n50", "c2", "c1", "c0", "c3", "c4"])
     ap.add_argument("--T", type=int, default=None, help="use only the first T locations")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--cpu-sample", type=int, default=2048, help="locations in the CPU oracle sample (0: skip)")
     ap.add_argument("--parity-sample", type=int, default=64, help="sampled locations checked against the oracle")
     ap.add_argument("--graph", default="auto", choices=["auto", "on", "off"],
                     help="run each step as one HIP-graph launch of a fixed-shape batch (auto: for uneven sizes)")
+    ap.add_argument("--burst", type=int, default=256, help="c4: requests per saturating burst (one step)")
+    ap.add_argument("--requests", type=int, default=2000, help="c4: requests per offered-load level")
+    ap.add_argument("--loads", default="0.5,0.8,0.95", help="c4: offered loads as fractions of saturation")
+    ap.add_argument("--budget-gib", type=int, default=32, help="c4: serving HBM budget")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -106,6 +110,8 @@ def main() -> int:
     import paper_1303_0383_amd as lagp
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c4":
+        return serve_bench(args, lagp, torch)
     dev = torch.device("cuda:0")
     w = workload(args.workload, args.T)
     prec = lagp.LAGP_PREC_FP64 if args.precision == "fp64" else lagp.LAGP_PREC_SCORE_FP32
@@ -237,6 +243,121 @@ def main() -> int:
         result["cpu_baseline"] = {"value": round(len(idx) / cpu_s, 2), "unit": "locations/s", "cores": threads,
                                   "kind": "oracle",
                                   "sample": f"{len(idx)} seeded locations of the same workload, {cpu_s:.1f} s, "
+                                            f"OpenMP over locations"}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def serve_bench(args, lagp, torch) -> int:
+    """Serving workload: N = 10^6 design points in [0,1]^4; requests of
+    1..512 locations with n in {32, 50, 64, 100} and N' in [1000, 4000],
+    n0 = 6, d = 0.3, g = 1e-5.  A step is one burst of --burst requests
+    submitted at once and drained (value: locations/s at saturation); then
+    Poisson arrivals at fractions of that rate give p50/p99 latency
+    (completion minus scheduled arrival, open loop)."""
+    import workloads
+    prm = workloads.C4_PARAMS
+    X, y, _ = workloads.c4_design()
+    D = lagp.Design(X, y)
+    S = lagp.Server(D, args.budget_gib << 30)
+    mono = lagp.lagp_monotonic_seconds
+
+    def submit(r):
+        return S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"])
+
+    burst = workloads.c4_requests(args.burst, 1.0)
+    burst_locs = sum(len(r.XX) for r in burst)
+
+    def step():
+        ts = [submit(r) for r in burst]
+        for t in ts:
+            S.wait(t)
+
+    for _ in range(args.warmup):
+        step()
+    step_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        step()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
+    elapsed = time.perf_counter() - t0
+    sat = burst_locs * args.steps / elapsed
+    mean_T = 256.5
+
+    levels = {}
+    for load in [float(v) for v in args.loads.split(",") if v]:
+        rate = load * sat / mean_T
+        reqs = workloads.c4_requests(args.requests, rate)
+        b0 = S.stats()
+        start = mono() + 0.05
+        tickets = []
+        for r in reqs:
+            delay = start + r.arrival_s - mono()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(submit(r))
+        lat, last = [], start
+        for r, t in zip(reqs, tickets):
+            o = S.wait(t)
+            lat.append(o.done - (start + r.arrival_s))
+            last = max(last, o.done)
+        b1 = S.stats()
+        locs = sum(len(r.XX) for r in reqs)
+        levels[f"{load:.2f}"] = {
+            "offered_req_per_s": round(rate, 1), "requests": len(reqs),
+            "achieved_locations_per_s": round(locs / (last - start), 1),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+            "batches": b1[0] - b0[0], "mean_batch_locations": round((b1[1] - b0[1]) / max(1, b1[0] - b0[0]), 1)}
+        print(f"# load {load:.2f}: {levels[f'{load:.2f}']}", file=sys.stderr, flush=True)
+    S.close()
+
+    # Roofline of the design kernel: one eager lagp_predict over the burst's
+    # locations (per-location sizes, size buckets), HIP events on its stream.
+    XX = np.concatenate([r.XX for r in burst])
+    n_per = np.concatenate([np.full(len(r.XX), r.n, np.int32) for r in burst])
+    M_per = np.concatenate([np.full(len(r.XX), r.ncand, np.int32) for r in burst])
+    dev = torch.device("cuda:0")
+    XXd = torch.as_tensor(XX, device=dev)
+    npd, mpd = torch.as_tensor(n_per, device=dev), torch.as_tensor(M_per, device=dev)
+    D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd)
+    torch.cuda.synchronize()
+    lagp.lagp_timing_enable(D.handle, True)
+    lagp.lagp_phase_times(D.handle)
+    D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd)
+    torch.cuda.synchronize()
+    knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+    lagp.lagp_timing_enable(D.handle, False)
+    flops = sum(design_flops(int(a), int(b), 4, prm["n0"]) for a, b in zip(n_per, M_per))
+    achieved = flops / (des_ms / 1e3) / 1e12
+    roofline = {"kernel": "design_kernel", "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(des_ms / max(launches, 1), 3), "launches_per_step": launches,
+                "flops_per_launch": flops / max(launches, 1), "knn_ms_per_burst": round(knn_ms, 3)}
+
+    result = {
+        "metric": METRIC, "value": round(sat, 1), "unit": "locations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c4", "N": len(X), "p": 4, "n0": prm["n0"], "d": prm["d"], "g": prm["g"],
+                   "burst_requests": args.burst, "burst_locations": burst_locs, "budget_gib": args.budget_gib},
+        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),
+        "serving": levels, "roofline": roofline,
+    }
+    if args.cpu_sample > 0:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        k = min(args.cpu_sample, 96, len(XX))
+        idx = np.sort(np.random.default_rng(20130383).choice(len(XX), k, replace=False))
+        tc = time.perf_counter()
+        oracle.batch(X, y, XX[idx], prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"],
+                     n_per=n_per[idx], M_per=M_per[idx], threads=threads)
+        cpu_s = time.perf_counter() - tc
+        result["cpu_baseline"] = {"value": round(k / cpu_s, 2), "unit": "locations/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"{k} seeded locations of the serving burst, {cpu_s:.1f} s, "
                                             f"OpenMP over locations"}
     print(json.dumps(result), flush=True)
     return 0

@@ -184,6 +184,48 @@ void lagp_batch_destroy(lagp_batch *batch);
  * global memory, 1 in LDS when they fit.  Applies to later calls on `design`. */
 int lagp_design_set_variant(lagp_design *design, int32_t threads, int32_t coords);
 
+/* ---- Serving: continuous batching of requests under an HBM budget.
+ *
+ * A server owns a worker thread, a HIP stream and a device arena of
+ * hbm_budget_bytes.  Submitted requests wait in a FIFO queue; whenever the
+ * device is free the worker runs, as one batch, the oldest request together
+ * with every later queued request of the same model (n0, d, g, precision)
+ * while the batch's device footprint -- its plan workspace, inputs and
+ * outputs -- fits the arena.  Each location's arithmetic is independent of
+ * the batch it runs in (locations are independent, Section 4.1): a request's
+ * results are bitwise the same alone or mixed with other traffic.
+ * All server arrays are HOST memory; inputs are copied at submission.
+ * Calls are thread-safe.  The server must be destroyed before its design. */
+typedef struct lagp_server lagp_server;
+int lagp_server_create(const lagp_design *design, size_t hbm_budget_bytes, lagp_server **out);
+
+/* Queue T locations XX (host, T x p) with per-location n / N' (host int32[T],
+ * nullable: params values).  Checks as lagp_predict; params->flags must be 0.
+ * Returns LAGP_E_BUDGET when the request alone cannot fit the arena.  Does
+ * not wait for the device; *ticket identifies the request. */
+int lagp_server_submit(lagp_server *server, const double *XX, int32_t T, const lagp_params *params,
+                       const int32_t *n_per, const int32_t *ncand_per, uint64_t *ticket);
+
+/* Returns 1 and copies the results (host arrays, each nullable; sel is
+ * T x sel_stride with sel_stride >= the request's largest n) when the request
+ * is done, releasing the ticket; 0 while it is pending.  wait_ms: 0 polls,
+ * > 0 waits at most that long, < 0 waits for completion.  times (nullable)
+ * receives [submission, completion] in seconds on the monotonic clock of
+ * lagp_monotonic_seconds.  A failed batch returns its error code. */
+int lagp_server_poll(lagp_server *server, uint64_t ticket, int32_t wait_ms, double *mean, double *s2, int32_t *df,
+                     double *var, int32_t *sel, int64_t sel_stride, int8_t *status, double *times);
+
+/* Batches run, locations and requests completed, and seconds the worker spent
+ * running batches, since creation. */
+int lagp_server_stats(lagp_server *server, int64_t *batches, int64_t *locations, int64_t *requests,
+                      double *busy_seconds);
+
+/* Finish the queued requests, stop the worker and free the arena.  NULL is ignored. */
+void lagp_server_destroy(lagp_server *server);
+
+/* Seconds on the steady (monotonic) clock the server's timestamps use. */
+double lagp_monotonic_seconds(void);
+
 /* Device bytes of workspace lagp_predict needs for a batch of T locations
  * with the given maxima (for admission control by callers). */
 int lagp_workspace_bytes(const lagp_design *design, int64_t T, int32_t nmax, int32_t ncand_max,

@@ -5,7 +5,7 @@ The functions named ``lagp_*`` mirror the C entry points one to one and only
 marshal arguments: torch tensors on the GPU pass their data pointers and the
 current HIP stream.  Every step of the computation runs in the library's HIP
 kernels.  Importing this module fails if the library has not been built
-(``python -m paper_1303_0383_amd.build`` or ``__graft_entry__.build()``).
+(``python paper_1303_0383_amd/build.py`` or ``__graft_entry__.build()``).
 """
 from __future__ import annotations
 
@@ -31,7 +31,7 @@ import torch  # noqa: E402,F401
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                      "(python -m paper_1303_0383_amd.build)")
+                      "(python paper_1303_0383_amd/build.py)")
 
 _lib = C.CDLL(LIB_PATH)
 
@@ -60,10 +60,19 @@ _lib.lagp_batch_info.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)
 _lib.lagp_batch_destroy.argtypes = [_P]
 _lib.lagp_batch_destroy.restype = None
 _lib.lagp_design_set_variant.argtypes = [_P, C.c_int32, C.c_int32]
+_lib.lagp_server_create.argtypes = [_P, C.c_size_t, C.POINTER(_P)]
+_lib.lagp_server_submit.argtypes = [_P, _P, C.c_int32, C.POINTER(lagp_params), _P, _P, C.POINTER(C.c_uint64)]
+_lib.lagp_server_poll.argtypes = [_P, C.c_uint64, C.c_int32, _P, _P, _P, _P, _P, C.c_int64, _P, _P]
+_lib.lagp_server_stats.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]
+_lib.lagp_server_destroy.argtypes = [_P]
+_lib.lagp_server_destroy.restype = None
+_lib.lagp_monotonic_seconds.restype = C.c_double
 _lib.lagp_last_error.restype = C.c_char_p
 for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
            "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
-           "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant"):
+           "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant",
+           "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -188,6 +197,46 @@ def lagp_batch_destroy(batch) -> None:
 
 def lagp_design_set_variant(design, threads: int, coords: int) -> None:
     _check(_lib.lagp_design_set_variant(design, threads, coords))
+
+
+def lagp_server_create(design, hbm_budget_bytes: int):
+    out = _P()
+    _check(_lib.lagp_server_create(design, hbm_budget_bytes, C.byref(out)))
+    return out
+
+
+def lagp_server_submit(server, XX, T: int, params: lagp_params, n_per=None, ncand_per=None) -> int:
+    """XX, n_per, ncand_per: host arrays."""
+    XX = np.ascontiguousarray(np.asarray(XX, dtype=np.float64))
+    hn = None if n_per is None else np.ascontiguousarray(np.asarray(n_per, dtype=np.int32))
+    hm = None if ncand_per is None else np.ascontiguousarray(np.asarray(ncand_per, dtype=np.int32))
+    ticket = C.c_uint64()
+    _check(_lib.lagp_server_submit(server, _ptr(XX), T, C.byref(params), _ptr(hn), _ptr(hm), C.byref(ticket)))
+    return int(ticket.value)
+
+
+def lagp_server_poll(server, ticket: int, wait_ms: int, mean, s2, df, var, sel, sel_stride: int, status, times):
+    """Host numpy outputs (each may be None); returns 1 when done, 0 while pending."""
+    rc = _lib.lagp_server_poll(server, ticket, wait_ms, _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel),
+                               sel_stride, _ptr(status), _ptr(times))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def lagp_server_stats(server):
+    """(batches, locations, requests, busy_seconds)."""
+    b, l, r, s = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+    _check(_lib.lagp_server_stats(server, C.byref(b), C.byref(l), C.byref(r), C.byref(s)))
+    return b.value, l.value, r.value, s.value
+
+
+def lagp_server_destroy(server) -> None:
+    _lib.lagp_server_destroy(server)
+
+
+def lagp_monotonic_seconds() -> float:
+    return _lib.lagp_monotonic_seconds()
 
 
 def lagp_timing_enable(design, enable: bool) -> None:
@@ -327,3 +376,65 @@ class Batch:
         f(self._h, XX, out.mean, out.s2, out.df, out.var, out.sel, self.nmax if out.sel is None else out.sel.shape[1],
           out.status, stream)
         return out
+
+
+@dataclass
+class Served:
+    """Results of one served request (host arrays)."""
+    mean: np.ndarray
+    s2: np.ndarray
+    df: np.ndarray
+    var: np.ndarray
+    sel: np.ndarray
+    status: np.ndarray
+    submitted: float
+    done: float
+
+
+class Server:
+    """Owns a lagp_server: continuous batching of host-side requests."""
+
+    def __init__(self, design: Design, hbm_budget_bytes: int):
+        self.design = design
+        self._h = lagp_server_create(design.handle, int(hbm_budget_bytes))
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lagp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, XX, n0: int, n, ncand, d: float, g: float, precision: int = LAGP_PREC_FP64) -> int:
+        """n, ncand: ints or per-location int arrays."""
+        XX = np.asarray(XX, dtype=np.float64)
+        T = XX.shape[0]
+        n_arr = np.broadcast_to(np.asarray(n, dtype=np.int32), (T,))
+        m_arr = np.broadcast_to(np.asarray(ncand, dtype=np.int32), (T,))
+        prm = lagp_params(n0, int(n_arr.max()), int(m_arr.max()), d, g, precision, 0)
+        ticket = lagp_server_submit(self._h, XX, T, prm, n_arr, m_arr)
+        self._n[ticket] = (T, int(n_arr.max()))
+        return ticket
+
+    def poll(self, ticket: int, wait_ms: int = 0) -> Optional[Served]:
+        T, nmax = self._n[ticket]
+        out = Served(mean=np.empty(T), s2=np.empty(T), df=np.empty(T, np.int32), var=np.empty(T),
+                     sel=np.empty((T, nmax), np.int32), status=np.empty(T, np.int8), submitted=0.0, done=0.0)
+        times = np.zeros(2)
+        if not lagp_server_poll(self._h, ticket, wait_ms, out.mean, out.s2, out.df, out.var, out.sel, nmax,
+                                out.status, times):
+            return None
+        del self._n[ticket]
+        out.submitted, out.done = float(times[0]), float(times[1])
+        return out
+
+    def wait(self, ticket: int) -> Served:
+        return self.poll(ticket, wait_ms=-1)
+
+    def stats(self):
+        return lagp_server_stats(self._h)

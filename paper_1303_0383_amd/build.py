@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblagp.so")
-SOURCES = ["lagp_api.cpp", "knn.hip", "design.hip", "design_f64.hip", "design_f64_trim.hip", "design_mix.hip",
+SOURCES = ["lagp_api.cpp", "server.cpp", "knn.hip", "design.hip", "design_f64.hip", "design_f64_trim.hip", "design_mix.hip",
            "design_mix_trim.hip", "predict.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

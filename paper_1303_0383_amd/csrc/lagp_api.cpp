@@ -15,30 +15,9 @@
 #include <string>
 #include <vector>
 
-#include "lagp.h"
-#include "lagp_internal.h"
+#include "lagp_runtime.h"
 
-using lagp::DeviceDesign;
-
-struct lagp_design {
-    DeviceDesign dev;
-    int device = 0;
-    int num_cu = 0;
-    size_t max_lds = 0;
-    double* Xsoa = nullptr;
-    double* Xaos = nullptr;
-    double* y = nullptr;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    bool timing = false;
-    std::vector<hipEvent_t> ev;   // triples: before kNN, after kNN, after design
-    std::vector<int64_t> ev_launches;   // design-kernel launches per triple
-    std::string arch;                   // e.g. "gfx950"
-    int force_threads = 0;              // kernel-variant override (0: table or model)
-    int force_coords = -1;
-};
-
-namespace {
+namespace lagp_rt {
 
 thread_local std::string g_err;
 
@@ -101,10 +80,11 @@ int check_device(const lagp_design* d)
     return LAGP_OK;
 }
 
-const int64_t kChunk = (int64_t)1 << 17;   // locations per launch sequence
 const int32_t kBucketMax = 512;
 
-}  // namespace
+}  // namespace lagp_rt
+
+using namespace lagp_rt;
 
 extern "C" {
 
@@ -223,31 +203,7 @@ int lagp_knn(const lagp_design* design, const double* XX, int64_t T, int32_t M, 
 // workgroups finish together.  Enqueueing a plan launches kernels only: no
 // allocation, no host synchronisation and no memset, so it can be captured
 // into a HIP graph.
-namespace {
-
-struct Bucket {
-    int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
-    int64_t first = 0, count = 0;   // range of the chunk's work list
-    lagp::DesignPlan plan;
-};
-
-struct Chunk {
-    int64_t t0 = 0, T = 0;
-    int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
-    std::vector<Bucket> buckets;
-    lagp::DesignPlan redo;   // FP64 plan for locations the mixed mode could not finish
-};
-
-struct Plan {
-    lagp_params prm{};
-    int64_t T = 0;
-    int32_t nmax = 0, Mmax = 0;
-    bool uneven = false, mix = false, own_sel = false, own_status = false;
-    std::vector<Chunk> chunks;
-    std::vector<int32_t> order;   // chunk-relative locations, chunk c at [t0, t0 + T)
-    // workspace layout
-    size_t knn_b = 0, cand_b = 0, design_b = 0, order_b = 0, sel_b = 0, status_b = 0, redo_b = 0, total = 0;
-};
+namespace lagp_rt {
 
 int size_class(int32_t v, int32_t lo)
 {
@@ -313,13 +269,15 @@ void choose_variant(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, 
         }
 }
 
-int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int32_t Mmin, int32_t n0,
+int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int32_t Mmin, int32_t n0, int64_t count,
                 lagp::DesignPlan* plan)
 {
     std::string err;
     choose_variant(d, prec, nmax, Mmax, plan);
     if (lagp::design_plan(d->dev, nmax, Mmax, Mmin, n0, prec, d->num_cu, d->max_lds, plan, &err))
         return fail(LAGP_E_INVAL, err);
+    // no more persistent workgroups (and scratch slabs) than locations
+    plan->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(plan->blocks, count));
     return LAGP_OK;
 }
 
@@ -419,12 +377,12 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
             }
         }
         for (Bucket& b : c.buckets) {
-            int rc = plan_design(d, prm->precision, b.nmax, b.Mmax, b.Mmin, prm->n0, &b.plan);
+            int rc = plan_design(d, prm->precision, b.nmax, b.Mmax, b.Mmin, prm->n0, b.count, &b.plan);
             if (rc) return rc;
             design_b = std::max(design_b, lagp::design_workspace_bytes(b.plan));
         }
         if (P->mix) {
-            int rc = plan_design(d, LAGP_PREC_FP64, c.nmax, c.Mmax, c.Mmin, prm->n0, &c.redo);
+            int rc = plan_design(d, LAGP_PREC_FP64, c.nmax, c.Mmax, c.Mmin, prm->n0, c.T, &c.redo);
             if (rc) return rc;
             design_b = std::max(design_b, lagp::design_workspace_bytes(c.redo));
         }
@@ -464,16 +422,6 @@ int prepare_plan(const lagp_design* d, const Plan& P)
     return LAGP_OK;
 }
 
-struct Outputs {
-    double* mean;
-    double* s2;
-    int32_t* df;
-    double* var;
-    int32_t* sel;
-    int64_t sel_stride;
-    int8_t* status;
-};
-
 __global__ void collect_failed_kernel(const int8_t* __restrict__ status, int64_t T, int32_t* __restrict__ list,
                                       uint32_t* __restrict__ count)
 {
@@ -484,7 +432,8 @@ __global__ void collect_failed_kernel(const int8_t* __restrict__ status, int64_t
 // Enqueues the whole plan on stream s.  ws holds P.total bytes; order_dev is
 // the uploaded work list (uneven plans); n_per / ncand_per are device arrays.
 int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_dev, const int32_t* n_per,
-                 const int32_t* ncand_per, const double* XX, const Outputs& o, hipStream_t s, bool graph_safe)
+                 const int32_t* ncand_per, const double* XX, const Outputs& o, hipStream_t s, bool graph_safe,
+                 bool timing)
 {
     char* q = ws;
     void* knn_ws = q;                  q += P.knn_b;
@@ -496,7 +445,6 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
     int32_t* redo_list = (int32_t*)q;
     uint32_t* redo_count = (uint32_t*)(q + (P.redo_b ? P.redo_b - 256 : 0));
     const int p = d->dev.p;
-    const bool timing = d->timing && !graph_safe;
     for (const Chunk& c : P.chunks) {
         std::string err;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -576,7 +524,7 @@ int check_outputs(const Outputs& o, int32_t nmax)
     return LAGP_OK;
 }
 
-}  // namespace
+}  // namespace lagp_rt
 
 struct lagp_batch {
     lagp_design* design = nullptr;
@@ -654,7 +602,7 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         if (e == hipSuccess) e = hipStreamSynchronize(s);   // P.order is released on return
         if (e != hipSuccess) return hip_fail("work list copy", e);
     }
-    rc = enqueue_plan(d, P, (char*)d->ws, order_dev, n_per, ncand_per, XX, o, s, false);
+    rc = enqueue_plan(d, P, (char*)d->ws, order_dev, n_per, ncand_per, XX, o, s, false, d->timing);
     if (rc) return rc;
     if (prm->flags & LAGP_STRICT) {
         if (!status) return fail(LAGP_E_INVAL, "strict mode needs the status output");
@@ -757,7 +705,7 @@ int lagp_batch_enqueue(lagp_batch* b, const double* XX, double* mean, double* s2
     int rc = batch_args(b, XX, o);
     if (rc) return rc;
     return enqueue_plan(b->design, b->plan, b->mem, b->order, b->n_per, b->ncand_per, XX, o, (hipStream_t)stream,
-                        true);
+                        true, false);
 }
 
 int lagp_batch_launch_graph(lagp_batch* b, const double* XX, double* mean, double* s2, int32_t* df, double* var,
@@ -772,7 +720,7 @@ int lagp_batch_launch_graph(lagp_batch* b, const double* XX, double* mean, doubl
         if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
         hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail("hipStreamBeginCapture", e);
-        rc = enqueue_plan(b->design, b->plan, b->mem, b->order, b->n_per, b->ncand_per, XX, o, b->cap, true);
+        rc = enqueue_plan(b->design, b->plan, b->mem, b->order, b->n_per, b->ncand_per, XX, o, b->cap, true, false);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }

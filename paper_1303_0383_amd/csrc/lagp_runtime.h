@@ -1,0 +1,91 @@
+// lagp_runtime.h -- internal host runtime shared by the entry points in
+// lagp_api.cpp and the serving engine in server.cpp: the device-resident
+// design, error reporting, and the batch planner (per-location size checks,
+// size buckets, longest-first work lists, kernel-variant choice, workspace
+// layout) with its capture-safe launch sequence.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "lagp.h"
+#include "lagp_internal.h"
+
+struct lagp_design {
+    lagp::DeviceDesign dev;
+    int device = 0;
+    int num_cu = 0;
+    size_t max_lds = 0;
+    double* Xsoa = nullptr;
+    double* Xaos = nullptr;
+    double* y = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // triples: before kNN, after kNN, after design
+    std::vector<int64_t> ev_launches;   // design-kernel launches per triple
+    std::string arch;                   // e.g. "gfx950"
+    int force_threads = 0;              // kernel-variant override (0: table or model)
+    int force_coords = -1;
+};
+
+namespace lagp_rt {
+
+const int64_t kChunk = (int64_t)1 << 17;   // locations per launch sequence
+
+int fail(int code, const std::string& msg);
+int hip_fail(const char* what, hipError_t e);
+bool is_device_ptr(const void* p);
+int check_device(const lagp_design* d);
+
+struct Bucket {
+    int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
+    int64_t first = 0, count = 0;   // range of the chunk's work list
+    lagp::DesignPlan plan;
+};
+
+struct Chunk {
+    int64_t t0 = 0, T = 0;
+    int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
+    std::vector<Bucket> buckets;
+    lagp::DesignPlan redo;   // FP64 plan for locations the mixed mode could not finish
+};
+
+struct Plan {
+    lagp_params prm{};
+    int64_t T = 0;
+    int32_t nmax = 0, Mmax = 0;
+    bool uneven = false, mix = false, own_sel = false, own_status = false;
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> order;   // chunk-relative locations, chunk c at [t0, t0 + T)
+    // workspace layout
+    size_t knn_b = 0, cand_b = 0, design_b = 0, order_b = 0, sel_b = 0, status_b = 0, redo_b = 0, total = 0;
+};
+
+struct Outputs {
+    double* mean;
+    double* s2;
+    int32_t* df;
+    double* var;
+    int32_t* sel;
+    int64_t sel_stride;
+    int8_t* status;
+};
+
+// Checks parameters and per-location sizes (host arrays, nullable) and builds
+// the plan for T locations.
+int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
+               bool have_sel, bool have_status, Plan* P);
+// Host-side kernel set-up for every variant the plan launches (outside capture).
+int prepare_plan(const lagp_design* d, const Plan& P);
+// Enqueues the plan on stream s: kernel launches only.  ws holds P.total
+// bytes; order_dev is the uploaded work list of an uneven plan; n_per and
+// ncand_per are device arrays (nullable for uniform sizes).
+// With `timing` the phases are bracketed by HIP events kept on the design.
+int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_dev, const int32_t* n_per,
+                 const int32_t* ncand_per, const double* XX, const Outputs& o, hipStream_t s, bool graph_safe,
+                 bool timing);
+int check_outputs(const Outputs& o, int32_t nmax);
+
+}  // namespace lagp_rt

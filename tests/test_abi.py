@@ -19,7 +19,12 @@ def _declared():
 
 @pytest.fixture(scope="module")
 def lib():
-    from paper_1303_0383_amd import build
+    import importlib.util
+    import torch  # noqa: F401  (one HIP runtime: torch's, as in the package)
+    spec = importlib.util.spec_from_file_location("_lagp_hipbuild",
+                                                  os.path.join(ROOT, "paper_1303_0383_amd", "build.py"))
+    build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(build)
     if not os.path.exists(build.LIB):
         build.build()
     return ctypes.CDLL(build.LIB)
