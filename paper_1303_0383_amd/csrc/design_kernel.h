@@ -176,6 +176,54 @@ __device__ __forceinline__ void wave_pick(double& v, int& i, int& s)
     pick<MAX>(v, i, s, __shfl_xor(v, 32), __shfl_xor(i, 32), __shfl_xor(s, 32));
 }
 
+// ---- the per-workgroup global slab through a buffer descriptor: one
+// per-thread offset register and uniform (scalar) slot and row offsets, so no
+// address registers per (slot, row) pair; accesses past the slab read 0 and
+// are not written.
+typedef unsigned int lagp_u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, int voff, int soff, double& v)
+{
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, int voff, int soff, float& v)
+{
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int voff, int soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lagp_u32x2, v), r, voff, soff, 0);
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+
+// Squared distance from the uniform point a to the candidate whose P
+// coordinates sit in the slab at byte offsets soff + k * cstride (+ voff).
+template <int P>
+__device__ __forceinline__ double sqdist_slab(const double* __restrict__ a, __amdgpu_buffer_rsrc_t r, int voff,
+                                              int soff, int cstride)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double c;
+        bload(r, voff, soff + k * cstride, c);
+        const double t = a[k] - c;
+        s += t * t;
+    }
+    return s;
+}
+
 // Four consecutive LDS floats (16-byte aligned start).
 __device__ __forceinline__ void ld4(const float* p, float* o)
 {
@@ -223,6 +271,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
     TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)(p + 1) * Mpad));
     double* Xc = CL ? Xcl : Xcg;
+    const __amdgpu_buffer_rsrc_t slab = slab_rsrc(Xcg, (uint32_t)(A.scratch_stride * sizeof(double)));
+    const int voff_c = tid * (int)sizeof(double);     // coordinate element of slot k = 0
+    const int voff_w = tid * (int)sizeof(TW);         // tile-row element of slot k = 0
+    const int wbase = CL ? 0 : (p + 1) * Mpad * (int)sizeof(double);   // tile rows after the coordinates
     const int rlds = A.rlds;
     const int G0 = RREG + rlds;   // first global row
     for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = 0.0;
@@ -277,12 +329,14 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (slot < M) {
                 const int c = cand[slot];
                 ci[k] = c;
-                Xc[(int64_t)p * Mpad + slot] = A.y[c];
+                if (CL) Xc[(int64_t)p * Mpad + slot] = A.y[c];
+                else bstore(slab, voff_c, (p * Mpad + k * DT) * (int)sizeof(double), A.y[c]);
                 const double* xc = A.Xaos + (int64_t)c * p;
                 double sq = 0.0;
                 for (int kk = 0; kk < p; ++kk) {
                     const double ck = xc[kk];
-                    Xc[(int64_t)kk * Mpad + slot] = ck;
+                    if (CL) Xc[(int64_t)kk * Mpad + slot] = ck;
+                    else bstore(slab, voff_c, (kk * Mpad + k * DT) * (int)sizeof(double), ck);
                     const double tt = xp[kk] - ck;
                     sq += tt * tt;
                 }
@@ -291,12 +345,16 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 v[k] = one_eta;
             } else {
                 ci[k] = 0x7fffffff;
-                Xc[(int64_t)p * Mpad + slot] = 0.0;
+                if (CL) Xc[(int64_t)p * Mpad + slot] = 0.0;
+                else bstore(slab, voff_c, (p * Mpad + k * DT) * (int)sizeof(double), 0.0);
                 d2[k] = INFINITY;
                 cov[k] = 0.0;
                 v[k] = one_eta;
                 chosen |= 1u << k;
-                for (int kk = 0; kk < p; ++kk) Xc[(int64_t)kk * Mpad + slot] = 0.0;
+                for (int kk = 0; kk < p; ++kk) {
+                    if (CL) Xc[(int64_t)kk * Mpad + slot] = 0.0;
+                    else bstore(slab, voff_c, (kk * Mpad + k * DT) * (int)sizeof(double), 0.0);
+                }
             }
         }
 
@@ -361,15 +419,18 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             double ax, acc[CPT];
             if (P > 0) {
                 ax = exp(-div_by(sqdist_lds<P>(xsp, xl, 1, p), theta, rtheta));
-if (full) {
+                // K(s, c): coordinates from LDS, or from the slab.
+                auto sqd = [&](int k) {
+                    if constexpr (CL) return sqdist_lds<P>(xsp, Xc + tid + k * DT, Mpad, p);
+                    else return sqdist_slab<(P > 0 ? P : 1)>(xsp, slab, voff_c, k * DT * (int)sizeof(double),
+                                                             Mpad * (int)sizeof(double));
+                };
+                if (full) {
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k)
-                        acc[k] = exp(-div_by(sqdist_lds<P>(xsp, Xc + tid + k * DT, Mpad, p), theta, rtheta));
+                    for (int k = 0; k < CPT; ++k) acc[k] = exp(-div_by(sqd(k), theta, rtheta));
                 } else {
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k)
-                        acc[k] = k < kact ? exp(-div_by(sqdist_lds<P>(xsp, Xc + tid + k * DT, Mpad, p), theta, rtheta))
-                                          : 0.0;
+                    for (int k = 0; k < CPT; ++k) acc[k] = k < kact ? exp(-div_by(sqd(k), theta, rtheta)) : 0.0;
                 }
             } else {
                 double sqx = 0.0, sq[CPT];
@@ -402,13 +463,13 @@ if (full) {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (u < gcount) {
-                        const TW* row = Wg + (int64_t)u * Mpad + tid;
-if (full) {
+                        const int rb = wbase + u * Mpad * (int)sizeof(TW);
+                        if (full) {
 #pragma unroll
-                            for (int k = 0; k < CPT; ++k) pre[u][k] = row[k * DT];
+                            for (int k = 0; k < CPT; ++k) bload(slab, voff_w, rb + k * DT * (int)sizeof(TW), pre[u][k]);
                         } else {
 #pragma unroll
-                            for (int k = 0; k < CPT; ++k) pre[u][k] = row[koff[k]];
+                            for (int k = 0; k < CPT; ++k) bload(slab, voff_w, rb + koff[k] * (int)sizeof(TW), pre[u][k]);
                         }
                     }
             }
@@ -514,13 +575,15 @@ if (full) {
 #pragma unroll
                     for (int u = 0; u < U; ++u)
                         if (u < nb2) {
-                            const TW* row = Wg + (int64_t)(l2 + u - G0) * Mpad + tid;
-if (full) {
+                            const int rb = wbase + (l2 + u - G0) * Mpad * (int)sizeof(TW);
+                            if (full) {
 #pragma unroll
-                                for (int k = 0; k < CPT; ++k) nxt[u][k] = row[k * DT];
+                                for (int k = 0; k < CPT; ++k)
+                                    bload(slab, voff_w, rb + k * DT * (int)sizeof(TW), nxt[u][k]);
                             } else {
 #pragma unroll
-                                for (int k = 0; k < CPT; ++k) nxt[u][k] = row[koff[k]];
+                                for (int k = 0; k < CPT; ++k)
+                                    bload(slab, voff_w, rb + koff[k] * (int)sizeof(TW), nxt[u][k]);
                             }
                         }
 #pragma unroll
@@ -575,14 +638,14 @@ if (full) {
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
             } else {
-                TW* row = Wg + (int64_t)(i - G0) * Mpad + tid;
+                const int rb = wbase + (i - G0) * Mpad * (int)sizeof(TW);
                 if (full) {
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
+                    for (int k = 0; k < CPT; ++k) bstore(slab, voff_w, rb + k * DT * (int)sizeof(TW), (TW)r[k]);
                 } else {
 #pragma unroll
                     for (int k = 0; k < CPT; ++k)
-                        if (k < kact) row[k * DT] = (TW)r[k];
+                        if (k < kact) bstore(slab, voff_w, rb + k * DT * (int)sizeof(TW), (TW)r[k]);
                 }
             }
 
