@@ -57,7 +57,9 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     // Option A: coordinates in LDS.  Option B: coordinates in global memory.
     // Cost: bytes read from global memory per location.
     const int pc = p + 1;   // coordinate rows plus the response
-    const int rregA = rreg_for(dt, cpt, true, mix), rregB = rreg_for(dt, cpt, false, mix);
+    // Trimmed variant when some location leaves a whole slot column empty.
+    const bool trim = cpt > 1 && Mmin <= (cpt - 1) * dt;
+    const int rregA = rreg_for(dt, cpt, true, mix, trim), rregB = rreg_for(dt, cpt, false, mix, trim);
     const int remA = rows > rregA ? rows - rregA : 0, remB = rows > rregB ? rows - rregB : 0;
     long long costA = -1, costB;
     int rldsA = 0;
@@ -74,8 +76,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     plan->threads = dt;
     plan->p = p;
     plan->lds_limit = max_lds;
-    // Trimmed variant when some location leaves a whole slot column empty.
-    plan->trim = cpt > 1 && Mmin <= (cpt - 1) * dt;
+    plan->trim = trim;
     plan->mix = mix;
     plan->rreg = cl ? rregA : rregB;
     plan->rlds = cl ? rldsA : rldsB;

@@ -32,6 +32,7 @@
 // else in the same slab.
 #pragma once
 #include <hip/hip_runtime.h>
+
 #include <math.h>
 #include <stdint.h>
 
@@ -137,16 +138,45 @@ __device__ __forceinline__ double sqdist_lds(const double* __restrict__ a, const
     return s;
 }
 
-// Rows of the whitened tile kept in registers for a workgroup size and slot
-// count.  With 256 threads (one wave per SIMD) a lane can hold 512 registers,
-// the upper half as accumulation registers the compiler uses as spill space;
-// with 512 threads a lane has 256.
-__host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = false)
+// Rows of the whitened tile kept in registers for a workgroup size, slot
+// count, coordinate placement, tile precision and trimming: the largest
+// multiple of 4 that compiles without scratch spills (measured for P = 8),
+// except where timing favoured a few more rows despite a small spill.
+// With 256 threads (one wave per SIMD) a lane can hold 512 registers, the
+// upper half as accumulation registers; with 512 threads a lane has 256.
+__host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = false, bool trim = false)
 {
-    return mix ? (dt == 256 ? (cpt >= 8 ? 8 : cpt == 4 ? (cl ? 24 : 16) : cpt == 2 ? 48 : 64)
-                            : (cpt >= 4 ? 0 : cpt == 2 ? 8 : 32))
-               : (dt == 256 ? (cpt >= 16 ? 0 : cpt == 8 ? 4 : cpt == 4 ? (cl ? 16 : 12) : cpt == 2 ? 32 : 64)
-                            : (cpt >= 4 ? 0 : cpt == 2 ? 4 : 16));
+    if (dt == 256) {
+        if (!mix) {
+            switch (cpt) {
+            case 1: return cl ? 88 : 80;
+            case 2: return (cl || trim) ? 44 : 40;
+            case 4: return (cl || trim) ? 20 : 16;
+            // 8 rows spill 40 bytes per lane here, and still stream fewer tile rows
+            default: return (cl && !trim) ? 8 : (cl || trim) ? 4 : 0;
+            }
+        }
+        switch (cpt) {
+        case 1: return 128;
+        case 2: return (cl || trim) ? 96 : 88;
+        case 4: return (cl || trim) ? 44 : 36;
+        default: return (cl || trim) ? 16 : 8;
+        }
+    }
+    if (!mix) {
+        switch (cpt) {
+        case 1: return 24;
+        case 2: return 12;
+        case 4: return 4;
+        default: return 0;
+        }
+    }
+    switch (cpt) {
+    case 1: return 64;
+    case 2: return 28;
+    case 4: return trim ? 12 : 8;
+    default: return 0;
+    }
 }
 
 // Rows per prefetch block of the global part of the tile (two blocks are in
@@ -713,7 +743,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 template <int DT, int CPT, int P, bool CL, bool MIX, bool TRIM>
 static int launch_design(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    constexpr int RREG = rreg_for(DT, CPT, CL, MIX);
+    constexpr int RREG = rreg_for(DT, CPT, CL, MIX, TRIM);
     auto kern = design_kernel<DT, CPT, RREG, P, CL, MIX, TRIM>;
     if (!a) {
         // Plans of one variant may differ in LDS size and a captured graph may

@@ -40,6 +40,7 @@ typedef unsigned __int128 u128;
 #define KNN_BINS 64
 #define KNN_TILE 256
 #define KNN_MAX_PASSES 18
+#define KNN_STAGE 16   // collected indices staged per thread before one slot reservation
 
 struct KnnState {
     uint64_t lo_hi, lo_lo;   // window lower bound (128-bit key)
@@ -265,8 +266,10 @@ __global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, int64_t T, int32
     if (!s.settled) atomicAdd(unsettled, 1u);
 }
 
-// Collect: keys below the window go straight to idx[t][*]; keys inside the
-// window go to the bucket with their full key.
+// Collect: keys below the window go to idx[t][*]; keys inside the window go
+// to the bucket with their full key.  When the design is split over several
+// blocks (gridDim.y > 1) a location's output slots are reserved with atomics,
+// KNN_STAGE indices at a time from a per-thread LDS stage.
 template <int P>
 __global__ void __launch_bounds__(KNN_THREADS)
 knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double* __restrict__ XX,
@@ -286,6 +289,8 @@ knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const doub
     u128 lo = 0, hi = 0;
     double xr[P > 0 ? P : 1];
     double* xl = tile + (size_t)KNN_TILE * p + tid;  // P == 0: x in LDS
+    int32_t* stage = (int32_t*)(tile + (size_t)KNN_TILE * p + (P > 0 ? 0 : (size_t)KNN_THREADS * p));
+    int ns = 0;   // staged indices of this thread
     const double* x = P > 0 ? xr : xl;
     uint32_t nbelow = 0, nbkt = 0;
     if (active) {
@@ -317,8 +322,17 @@ knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const doub
             const int64_t gi = base + ii;
             u128 key = ((u128)bits << 31) | (uint64_t)gi;
             if (bits < lo_d || key < lo) {
-                uint32_t slot = split ? atomicAdd(counts + 2 * t, 1u) : nbelow++;
-                out[slot] = (int32_t)gi;
+                if (!split) {
+                    out[nbelow++] = (int32_t)gi;
+                } else {
+                    stage[ns * KNN_THREADS + tid] = (int32_t)gi;
+                    if (++ns == KNN_STAGE) {
+                        const uint32_t b0 = atomicAdd(counts + 2 * t, (uint32_t)KNN_STAGE);
+#pragma unroll
+                        for (int j = 0; j < KNN_STAGE; ++j) out[b0 + j] = stage[j * KNN_THREADS + tid];
+                        ns = 0;
+                    }
+                }
             } else if (key < hi) {
                 uint32_t slot = split ? atomicAdd(counts + 2 * t + 1, 1u) : nbkt++;
                 if (slot < (uint32_t)bucket_max) {
@@ -327,6 +341,10 @@ knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const doub
                 }
             }
         }
+    }
+    if (split && active && ns > 0) {
+        const uint32_t b0 = atomicAdd(counts + 2 * t, (uint32_t)ns);
+        for (int j = 0; j < ns; ++j) out[b0 + j] = stage[j * KNN_THREADS + tid];
     }
     if (!split && active) {
         counts[2 * t] = nbelow;
@@ -453,7 +471,7 @@ static void knn_lds(int p, size_t* lds_hist, size_t* lds_coll)
 {
     const size_t lds_x = p <= 8 ? 0 : (size_t)KNN_THREADS * p * sizeof(double);
     *lds_hist = (size_t)KNN_TILE * p * sizeof(double) + (size_t)KNN_BINS * KNN_THREADS * 2 + lds_x;
-    *lds_coll = (size_t)KNN_TILE * p * sizeof(double) + lds_x;
+    *lds_coll = (size_t)KNN_TILE * p * sizeof(double) + lds_x + (size_t)KNN_STAGE * KNN_THREADS * sizeof(int32_t);
 }
 
 int knn_prepare(int p, size_t max_lds, std::string* err)
