@@ -218,7 +218,24 @@ def main() -> int:
     rng = np.random.default_rng(20130383)
 
     # Parity of sampled outputs against the FP64 oracle.
-    if args.parity_sample > 0:
+    if args.parity_sample > 0 and args.precision == "fp32":
+        # Mixed precision: per-step agreement under replay, sequence identity,
+        # mean RMS difference from the FP64 oracle over sd(y), and the FP64
+        # prediction from the chosen indices against the oracle's.
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import mixed_metrics
+        idx = np.sort(rng.choice(T, min(args.parity_sample, T), replace=False))
+        try:
+            m = mixed_metrics(w.X, w.y, w.XX, w.n0, w.n, w.ncand, w.d, w.g, res, idx=idx,
+                              n_per=w.n_per, M_per=w.ncand_per)
+            m = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in m.items()}
+            m["selection_bar_met"] = m["step_agreement"] >= 0.99
+            m["mean_rms_bar_met"] = m["mean_rms_over_sd"] <= 1e-4
+            m["ok"] = m["selection_bar_met"] and m["prediction_parity"] <= 1e-9
+        except AssertionError as e:
+            m = {"ok": False, "error": str(e)}
+        result["parity"] = {"locations": len(idx), "kind": "mixed", **m}
+    elif args.parity_sample > 0:
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from parity import compare
         idx = np.sort(rng.choice(T, min(args.parity_sample, T), replace=False))

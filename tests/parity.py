@@ -83,7 +83,7 @@ def compare(X, y, XX, n0, n, M, d, g, res, idx=None, n_per=None, M_per=None):
     return worst
 
 
-def mixed_metrics(X, y, XX, n0, n, M, d, g, res, idx=None):
+def mixed_metrics(X, y, XX, n0, n, M, d, g, res, idx=None, n_per=None, M_per=None):
     """Mixed-precision quality against the FP64 oracle.
 
     * step agreement: the oracle replays the GPU's choices; a greedy step
@@ -102,13 +102,15 @@ def mixed_metrics(X, y, XX, n0, n, M, d, g, res, idx=None):
     sdy = float(np.std(y))
     notpd = 0
     for t in idx:
-        rc, s_o, o, _ = oracle.local(X, y, XX[t], n0, n, M, d, g)
+        nt = int(n_per[t]) if n_per is not None else n
+        mt = int(M_per[t]) if M_per is not None else M
+        rc, s_o, o, _ = oracle.local(X, y, XX[t], n0, nt, mt, d, g)
         if res["status"][t] != 0:
             assert rc == oracle.NOTPD, f"location {t}: GPU NOTPD where the FP64 oracle succeeds"
             notpd += 1
             continue
-        s_g = res["sel"][t, :n]
-        rc2, _, o_r, diag = oracle.local(X, y, XX[t], n0, n, M, d, g, replay=s_g)
+        s_g = res["sel"][t, :nt]
+        rc2, _, o_r, diag = oracle.local(X, y, XX[t], n0, nt, mt, d, g, replay=s_g)
         a1, ach = diag[n0:, 0], diag[n0:, 2]
         ok = (a1 - ach) <= GAP_TOL * np.where(a1 > 0, a1, 1.0)
         steps += len(ok)

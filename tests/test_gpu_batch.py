@@ -204,3 +204,24 @@ def test_batch_invalid_arguments(c1, lagp):
         lagp.lagp_batch_enqueue(B.handle, XXd, out.mean, out.s2, out.df, out.var, out.sel, 5, out.status)
     B.close()
     del dev_sizes
+
+
+def test_batch_multi_chunk_graph(c1, lagp):
+    """A batch of more than 2^17 locations (several launch chunks) as one graph
+    equals lagp_predict; ragged per-location sizes and the last partial chunk."""
+    import torch
+    w, D = c1
+    T = (1 << 17) + 1234
+    r = np.random.default_rng(41)
+    XX = r.uniform(-2.0, 2.0, (T, 2))
+    n_per = r.integers(6, 13, T).astype(np.int32)
+    M_per = r.integers(16, 65, T).astype(np.int32)
+    ref = gpu_predict(D, XX, w.n0, int(n_per.max()), int(M_per.max()), w.d, w.g, n_per=n_per, M_per=M_per)
+    B = lagp.Batch(D, T, w.n0, 0, 0, w.d, w.g, n_per=n_per, ncand_per=M_per)
+    XXd = torch.as_tensor(XX, device="cuda:0")
+    for rep in range(2):
+        _same(_host(B.run(XXd, graph=True)), ref, n_per)
+    B.close()
+    idx = r.choice(T, 6, replace=False)
+    summary = compare(w.X, w.y, XX, w.n0, 0, 0, w.d, w.g, ref, idx=idx, n_per=n_per, M_per=M_per)
+    print("multi-chunk", summary)
