@@ -56,7 +56,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     const size_t avail = max_lds - fixed;
     // Option A: coordinates in LDS.  Option B: coordinates in global memory.
     // Cost: bytes read from global memory per location.
-    const int pc = p + 1;   // coordinate rows plus the response
+    const int pc = p;   // coordinate rows (the chosen response is read from the design)
     // Trimmed variant when some location leaves a whole slot column empty.
     const bool trim = cpt > 1 && Mmin <= (cpt - 1) * dt;
     const int rregA = rreg_for(dt, cpt, true, mix, trim), rregB = rreg_for(dt, cpt, false, mix, trim);

@@ -295,16 +295,16 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     int* ctl = forced + nmax;               // [4]  location
     size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
     off = (off + 15) & ~(size_t)15;
-    double* Xcl = (double*)((char*)smem + off);              // [p+1][Mpad] when CL: coordinates, y
-    TW* Wl = (TW*)(Xcl + (CL ? (size_t)(p + 1) * Mpad : 0));  // [rlds][Mpad]
+    double* Xcl = (double*)((char*)smem + off);              // [p][Mpad] when CL: coordinates
+    TW* Wl = (TW*)(Xcl + (CL ? (size_t)p * Mpad : 0));  // [rlds][Mpad]
 
     double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-    TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)(p + 1) * Mpad));
+    TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)p * Mpad));
     double* Xc = CL ? Xcl : Xcg;
     const __amdgpu_buffer_rsrc_t slab = slab_rsrc(Xcg, (uint32_t)(A.scratch_stride * sizeof(double)));
     const int voff_c = tid * (int)sizeof(double);     // coordinate element of slot k = 0
     const int voff_w = tid * (int)sizeof(TW);         // tile-row element of slot k = 0
-    const int wbase = CL ? 0 : (p + 1) * Mpad * (int)sizeof(double);   // tile rows after the coordinates
+    const int wbase = CL ? 0 : p * Mpad * (int)sizeof(double);   // tile rows after the coordinates
     const int rlds = A.rlds;
     const int G0 = RREG + rlds;   // first global row
     for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = 0.0;
@@ -359,8 +359,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (slot < M) {
                 const int c = cand[slot];
                 ci[k] = c;
-                if (CL) Xc[(int64_t)p * Mpad + slot] = A.y[c];
-                else bstore(slab, voff_c, (p * Mpad + k * DT) * (int)sizeof(double), A.y[c]);
                 const double* xc = A.Xaos + (int64_t)c * p;
                 double sq = 0.0;
                 for (int kk = 0; kk < p; ++kk) {
@@ -375,8 +373,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 v[k] = one_eta;
             } else {
                 ci[k] = 0x7fffffff;
-                if (CL) Xc[(int64_t)p * Mpad + slot] = 0.0;
-                else bstore(slab, voff_c, (p * Mpad + k * DT) * (int)sizeof(double), 0.0);
                 d2[k] = INFINITY;
                 cov[k] = 0.0;
                 v[k] = one_eta;
@@ -444,7 +440,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
                 for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
             }
-            const double ys = Xc[(int64_t)p * Mpad + s];
+            const double ys = A.y[cand[s]];   // one response per step: read from the design
             const double* xsp = P > 0 ? xs : xl;   // runtime dimension: read below from Xc
             double ax, acc[CPT];
             if (P > 0) {
