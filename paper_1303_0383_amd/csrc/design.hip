@@ -56,15 +56,18 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     const size_t avail = max_lds - fixed;
     // Option A: coordinates in LDS.  Option B: coordinates in global memory.
     // Cost: bytes read from global memory per location.
-    const int pc = p;   // coordinate rows (the chosen response is read from the design)
+    // Option A keeps the coordinates and the responses in LDS (one step needs
+    // one response, read there); option B keeps the coordinates in the
+    // global slab and reads the chosen response from the design.
+    const int pcA = p + 1, pc = p;
     // Trimmed variant when some location leaves a whole slot column empty.
     const bool trim = cpt > 1 && Mmin <= (cpt - 1) * dt;
     const int rregA = rreg_for(dt, cpt, true, mix, trim), rregB = rreg_for(dt, cpt, false, mix, trim);
     const int remA = rows > rregA ? rows - rregA : 0, remB = rows > rregB ? rows - rregB : 0;
     long long costA = -1, costB;
     int rldsA = 0;
-    if (avail >= pc * crow_bytes) {
-        rldsA = std::min<long long>(remA, (avail - pc * crow_bytes) / row_bytes);
+    if (avail >= pcA * crow_bytes) {
+        rldsA = std::min<long long>(remA, (avail - pcA * crow_bytes) / row_bytes);
         costA = global_row_reads(nmax, rregA + rldsA) * (long long)row_bytes;
     }
     const int rldsB = std::min<long long>(remB, avail / row_bytes);
@@ -82,7 +85,8 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     plan->rlds = cl ? rldsA : rldsB;
     plan->rglob = (cl ? remA : remB) - plan->rlds;
     plan->coords_lds = cl;
-    plan->lds_bytes = fixed + (cl ? pc * crow_bytes : 0) + (size_t)plan->rlds * row_bytes;
+    plan->lds_bytes = fixed + (cl ? pcA * crow_bytes : 0) + (size_t)plan->rlds * row_bytes;
+    plan->y_lds = cl;
     plan->scratch_per_block = align256((cl ? 0 : pc * crow_bytes) + (size_t)plan->rglob * row_bytes);
     plan->blocks = num_cu;
     plan->counter_bytes = 256;
@@ -132,6 +136,7 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
     a.scratch_stride = (int64_t)(plan.scratch_per_block / sizeof(double));
     a.rlds = plan.rlds;
     a.coords_lds = plan.coords_lds ? 1 : 0;
+    a.y_lds = plan.y_lds ? 1 : 0;
     a.nmax = L.n;
     a.order = L.order;
     a.count = L.count;

@@ -65,6 +65,7 @@ struct DesignArgs {
     double* scratch;
     int64_t scratch_stride;  // doubles per workgroup
     int rlds, coords_lds;
+    int y_lds;               // the candidates' responses follow the coordinates in LDS (CL only)
     int nmax;
     unsigned int* counter;
     const int32_t* order;    // nullable: work item -> location (else identity)
@@ -295,8 +296,9 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     int* ctl = forced + nmax;               // [4]  location
     size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
     off = (off + 15) & ~(size_t)15;
-    double* Xcl = (double*)((char*)smem + off);              // [p][Mpad] when CL: coordinates
-    TW* Wl = (TW*)(Xcl + (CL ? (size_t)p * Mpad : 0));  // [rlds][Mpad]
+    const int ylds = CL ? A.y_lds : 0;
+    double* Xcl = (double*)((char*)smem + off);              // [p (+1)][Mpad] when CL: coordinates (y)
+    TW* Wl = (TW*)(Xcl + (CL ? (size_t)(p + ylds) * Mpad : 0));  // [rlds][Mpad]
 
     double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
     TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)p * Mpad));
@@ -359,6 +361,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (slot < M) {
                 const int c = cand[slot];
                 ci[k] = c;
+                if (CL && ylds) Xc[(int64_t)p * Mpad + slot] = A.y[c];
                 const double* xc = A.Xaos + (int64_t)c * p;
                 double sq = 0.0;
                 for (int kk = 0; kk < p; ++kk) {
@@ -373,6 +376,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 v[k] = one_eta;
             } else {
                 ci[k] = 0x7fffffff;
+                if (CL && ylds) Xc[(int64_t)p * Mpad + slot] = 0.0;
                 d2[k] = INFINITY;
                 cov[k] = 0.0;
                 v[k] = one_eta;
@@ -440,7 +444,8 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
                 for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
             }
-            const double ys = A.y[cand[s]];   // one response per step: read from the design
+            // one response per step: from LDS when it holds them, else from the design
+            const double ys = (CL && ylds) ? Xc[(int64_t)p * Mpad + s] : A.y[cand[s]];
             const double* xsp = P > 0 ? xs : xl;   // runtime dimension: read below from Xc
             double ax, acc[CPT];
             if (P > 0) {

@@ -28,6 +28,7 @@
 // Squared distances are summed over coordinates left to right with no fused
 // multiply-add (this file is compiled with -ffp-contract=off).
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "lagp_internal.h"
@@ -49,6 +50,8 @@ struct KnnState {
     uint32_t bucket;         // keys inside the window (valid once settled)
     int32_t settled;         // 1: window final
     int32_t pass;            // passes run so far
+    int32_t count_below;     // 1: the window was estimated, the next pass counts the keys below it
+    int32_t misses;          // estimated windows that missed the M-th key
 };
 
 __device__ __forceinline__ u128 mk128(uint64_t h, uint64_t l) { return ((u128)h << 64) | l; }
@@ -124,6 +127,8 @@ __global__ void knn_init_kernel(KnnState* st, uint32_t* hist, int64_t T)
     s.bucket = 0;
     s.settled = 0;
     s.pass = 0;
+    s.count_below = 0;
+    s.misses = 0;
     st[t] = s;
     for (int b = 0; b < KNN_BINS; ++b) hist[t * KNN_BINS + b] = 0;
 }
@@ -144,7 +149,7 @@ template <int P>
 __global__ void __launch_bounds__(KNN_THREADS)
 knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double* __restrict__ XX,
                 int64_t T, int32_t M, KnnState* __restrict__ st, uint32_t* __restrict__ hist,
-                int64_t chunk)
+                uint32_t* __restrict__ belowc, int64_t chunk)
 {
     extern __shared__ double smem[];
     double* tile = smem;                                          // KNN_TILE * p
@@ -158,6 +163,8 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
 
     bool active = false;
     int kind = 0;
+    bool cbelow = false;
+    uint32_t nbelow = 0;   // keys below an estimated window (count_below)
     u128 lo = 0, hi = 0;
     int shift = 0;
     double xr[P > 0 ? P : 1];
@@ -167,6 +174,7 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
         KnnState s = st[t];
         active = !s.settled;
         kind = s.pass == 0 ? 0 : 1;
+        cbelow = s.count_below != 0;
         lo = mk128(s.lo_hi, s.lo_lo);
         hi = mk128(s.hi_hi, s.hi_lo);
         shift = ceil_log2_128(hi - lo) - 6;
@@ -205,13 +213,19 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
             for (int ii = 0; ii < count; ++ii) {
                 double d2 = tile_d2<P>(tile + ii * p, x, p);
                 uint64_t bits = (uint64_t)__double_as_longlong(d2);
-                if (bits < lo_d || bits > hi_d) continue;
+                if (bits > hi_d) continue;
+                if (bits < lo_d) { nbelow += cbelow ? 1u : 0u; continue; }
                 u128 key = ((u128)bits << 31) | (uint64_t)(base + ii);
-                if (key < lo || key >= hi) continue;
+                if (key < lo) { nbelow += cbelow ? 1u : 0u; continue; }
+                if (key >= hi) continue;
                 int b = (int)((key - lo) >> shift);
                 h[b * KNN_THREADS + tid] += 1;
             }
         }
+    }
+    if (active && cbelow && nbelow) {
+        if (gridDim.y == 1) belowc[t] += nbelow;
+        else atomicAdd(belowc + t, nbelow);
     }
     if (active) {
         uint32_t* hg = hist + t * KNN_BINS;
@@ -226,18 +240,80 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
 }
 
 // Choose the bin holding the M-th key; settle or narrow the window.
-__global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, int64_t T, int32_t M_all,
-                                  const int32_t* __restrict__ M_per, int32_t bucket_max, uint32_t* unsettled)
+// Key window of squared distances [a, b] (both non-negative): keys whose
+// distance bits lie in [bits(a), bits(b)]; the whole key range if empty.
+__device__ __forceinline__ void d2_window(double a, double b, u128* lo, u128* hi)
+{
+    const u128 top = (u128)1 << 94;
+    const uint64_t ab = (uint64_t)__double_as_longlong(a);
+    const uint64_t bb = (uint64_t)__double_as_longlong(b);
+    u128 nlo = (u128)ab << 31, nhi = (u128)(bb + 1) << 31;
+    if (nhi > top) nhi = top;
+    if (nlo >= nhi) { nlo = 0; nhi = top; }   // (non-finite distances) the whole key range
+    *lo = nlo;
+    *hi = nhi;
+}
+
+__device__ __forceinline__ double key_d2(u128 key)
+{
+    return __longlong_as_double((long long)(uint64_t)(key >> 31));
+}
+
+// On the design sample (mdiv = the sample stride) the target rank is
+// ceil(M / mdiv); bucket_max = 0 there keeps refining.
+__global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, uint32_t* belowc, int64_t T, int32_t M_all,
+                                  const int32_t* __restrict__ M_per, int32_t mdiv, int32_t bucket_max, double fac,
+                                  uint32_t* unsettled)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
     // Per-location sizes are clamped to the row length M_all (invalid sizes
     // are rejected before launch, or flagged by the design kernel).
-    const int32_t M = M_per ? (M_per[t] < M_all ? M_per[t] : M_all) : M_all;
+    int32_t M = M_per ? (M_per[t] < M_all ? M_per[t] : M_all) : M_all;
+    M = (M + mdiv - 1) / mdiv;
     KnnState s = st[t];
     if (s.settled) return;
     uint32_t* hg = hist + t * KNN_BINS;
     uint32_t cum = s.below;
+    if (s.count_below) {
+        // The window came from the sample: the pass counted the keys below it.
+        s.count_below = 0;
+        cum = belowc[t];
+        belowc[t] = 0;
+        uint32_t inwin = 0;
+        for (int k = 0; k < KNN_BINS; ++k) inwin += hg[k];
+        const u128 olo = mk128(s.lo_hi, s.lo_lo), ohi = mk128(s.hi_hi, s.hi_lo);
+        if (cum >= (uint32_t)M || cum + inwin < (uint32_t)M) {
+            const bool below = cum >= (uint32_t)M;
+            u128 lo, hi;
+            if (s.misses == 0) {
+                // First miss: an estimated window again, on the missed side and
+                // wider (squared distances by the factor 9^(2/p) = (3^(2/p))^2).
+                const double f = fac * fac;
+                if (below) d2_window(key_d2(olo) / f, key_d2(olo), &lo, &hi);
+                else d2_window(key_d2(ohi), key_d2(ohi - 1) * f, &lo, &hi);
+                if (below && hi > olo) hi = olo;
+                if (!below && lo < ohi) lo = ohi;
+                s.count_below = 1;
+            } else {
+                // Then the whole key range on the missed side, refined as usual:
+                // [0, lo) holding `cum` keys, or [hi, 2^94) above cum + inwin keys.
+                lo = below ? (u128)0 : ohi;
+                hi = below ? olo : ((u128)1 << 94);
+                s.below = below ? 0u : cum + inwin;
+            }
+            s.misses += 1;
+            s.lo_hi = hi64(lo); s.lo_lo = lo64(lo);
+            s.hi_hi = hi64(hi); s.hi_lo = lo64(hi);
+            s.bucket = 0;
+            s.pass += 1;
+            s.settled = 0;
+            st[t] = s;
+            for (int k = 0; k < KNN_BINS; ++k) hg[k] = 0;
+            atomicAdd(unsettled, 1u);
+            return;
+        }
+    }
     int b = 0;
     for (; b < KNN_BINS - 1; ++b) {
         if (cum + hg[b] >= (uint32_t)M) break;
@@ -245,7 +321,7 @@ __global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, int64_t T, int32
     }
     uint32_t inbin = hg[b];
     u128 lo, hi;
-    if (s.pass == 0) {
+    if (s.pass == 0) {   // octave histogram
         exp_bin_window(b, &lo, &hi);
     } else {
         u128 olo = mk128(s.lo_hi, s.lo_lo), ohi = mk128(s.hi_hi, s.hi_lo);
@@ -264,6 +340,29 @@ __global__ void knn_decide_kernel(KnnState* st, uint32_t* hist, int64_t T, int32
     st[t] = s;
     for (int k = 0; k < KNN_BINS; ++k) hg[k] = 0;
     if (!s.settled) atomicAdd(unsettled, 1u);
+}
+
+// From the window that holds the sample's ceil(M / stride)-th key, estimate
+// the full design's window: squared distances in [lo / fac, hi * fac] with
+// fac = 3^(2/p), i.e. expected ranks from M/3 to 3M where the neighbour count
+// grows like distance^p.  The next full pass counts the keys below it
+// (count_below); the decide kernel handles an estimate that misses.
+__global__ void knn_estimate_kernel(KnnState* st, int64_t T, double fac)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    KnnState s = st[t];
+    const u128 lo = mk128(s.lo_hi, s.lo_lo), hi = mk128(s.hi_hi, s.hi_lo);
+    u128 nlo, nhi;
+    d2_window(key_d2(lo) / fac, key_d2(hi - 1) * fac, &nlo, &nhi);
+    s.lo_hi = hi64(nlo); s.lo_lo = lo64(nlo);
+    s.hi_hi = hi64(nhi); s.hi_lo = lo64(nhi);
+    s.below = 0;
+    s.bucket = 0;
+    s.settled = 0;
+    s.pass = 1;
+    s.count_below = 1;
+    st[t] = s;
 }
 
 // Collect: keys below the window go to idx[t][*]; keys inside the window go
@@ -463,8 +562,27 @@ size_t knn_workspace_bytes(int64_t T, int32_t bucket_max)
     b += align256((size_t)T * KNN_BINS * sizeof(uint32_t));
     b += align256((size_t)T * 2 * sizeof(uint32_t));
     b += align256((size_t)T * bucket_max * 2 * sizeof(uint64_t));
+    b += align256((size_t)T * sizeof(uint32_t));   // keys below an estimated window
     b += align256(4 * sizeof(uint32_t));
     return b;
+}
+
+// Split a design of N rows over gridDim.y so that the grid covers the chip
+// about four times over, keeping at least 2 tiles per split and at most
+// 65280 rows per split (16-bit private histogram counters).
+static void knn_split(int64_t N, int64_t nblk, int num_cu, int64_t* chunk_out, int64_t* split_out)
+{
+    int64_t split = (4LL * num_cu + nblk - 1) / nblk;
+    int64_t max_split = (N + 2 * KNN_TILE - 1) / (2 * KNN_TILE);
+    if (split > max_split) split = max_split;
+    if (split < 1) split = 1;
+    if (split > 65535) split = 65535;
+    const int64_t max_chunk = 65280;
+    if (split < (N + max_chunk - 1) / max_chunk) split = (N + max_chunk - 1) / max_chunk;
+    int64_t chunk = (N + split - 1) / split;
+    chunk = (chunk + KNN_TILE - 1) / KNN_TILE * KNN_TILE;
+    *chunk_out = chunk;
+    *split_out = (N + chunk - 1) / chunk;
 }
 
 static void knn_lds(int p, size_t* lds_hist, size_t* lds_coll)
@@ -502,23 +620,18 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     uint32_t* hist = (uint32_t*)w; w += align256((size_t)T * KNN_BINS * sizeof(uint32_t));
     uint32_t* counts = (uint32_t*)w; w += align256((size_t)T * 2 * sizeof(uint32_t));
     uint64_t* bucket = (uint64_t*)w; w += align256((size_t)T * bucket_max * 2 * sizeof(uint64_t));
+    uint32_t* belowc = (uint32_t*)w; w += align256((size_t)T * sizeof(uint32_t));
     uint32_t* flags = (uint32_t*)w;  // [0] unsettled, [1] bad
 
     const int64_t nblk = (T + KNN_THREADS - 1) / KNN_THREADS;
-    // Split the design over gridDim.y so that the grid covers the chip about
-    // four times over, keeping at least 2 tiles per split.
-    int64_t split = (4LL * num_cu + nblk - 1) / nblk;
-    int64_t max_split = (D.N + 2 * KNN_TILE - 1) / (2 * KNN_TILE);
-    if (split > max_split) split = max_split;
-    if (split < 1) split = 1;
-    if (split > 65535) split = 65535;
-    // 16-bit private histogram counters: at most 65280 design rows per split.
-    const int64_t max_chunk = 65280;
-    if (split < (D.N + max_chunk - 1) / max_chunk) split = (D.N + max_chunk - 1) / max_chunk;
-    int64_t chunk = (D.N + split - 1) / split;
-    chunk = (chunk + KNN_TILE - 1) / KNN_TILE * KNN_TILE;
-    split = (D.N + chunk - 1) / chunk;
-
+    int64_t chunk, split, chunk_s = 0, split_s = 0;
+    knn_split(D.N, nblk, num_cu, &chunk, &split);
+    // Estimate each location's candidate radius on the design sample first
+    // when the sample holds enough rows (two cheap passes replace the first
+    // full octave pass).
+    const bool use_sample = D.Xsoa_s && D.Ns >= 2 * KNN_TILE && (int64_t)M * 8 <= D.N;
+    const double fac = pow(3.0, 2.0 / D.p);   // 3^(2/p)
+    if (use_sample) knn_split(D.Ns, nblk, num_cu, &chunk_s, &split_s);
     size_t lds_hist, lds_coll;
     knn_lds(D.p, &lds_hist, &lds_coll);
     if (lds_hist > max_lds) { *err = "input dimension too large for the kNN tile"; return -1; }
@@ -526,19 +639,37 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
 
     hipLaunchKernelGGL(knn_init_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st, hist, T);
     fill_u32(flags, 4, 0u, stream);
+    fill_u32(belowc, T, 0u, stream);
     const dim3 grid((unsigned)nblk, (unsigned)split);
-    // The first pass leaves a key window at most 2^93 wide and each later pass
-    // divides it by 64, so 17 passes always settle every location.  Without a
-    // host round trip (graph capture) all passes are launched; blocks whose
-    // locations have settled return at once.
+    const unsigned dgrid = (unsigned)((T + 255) / 256);
+    if (use_sample) {
+        // Octave pass and one refinement on the sample (never settling), then
+        // the estimated window for the full design.
+        const dim3 grid_s((unsigned)nblk, (unsigned)split_s);
+        for (int pass = 0; pass < 2; ++pass) {
+#define LAGP_KNN_HIST(PP) hipLaunchKernelGGL(knn_hist_kernel<PP>, grid_s, dim3(KNN_THREADS), lds_hist, stream, \
+                                             D.Xsoa_s, D.Ns, D.p, XX, T, M, st, hist, belowc, chunk_s)
+            LAGP_DISPATCH_P(D.p, LAGP_KNN_HIST);
+#undef LAGP_KNN_HIST
+            hipLaunchKernelGGL(knn_decide_kernel, dim3(dgrid), dim3(256), 0, stream, st, hist, belowc, T, M, M_per,
+                               (int32_t)KNN_SAMPLE_STRIDE, 0, fac, flags);
+        }
+        hipLaunchKernelGGL(knn_estimate_kernel, dim3(dgrid), dim3(256), 0, stream, st, T, fac);
+    }
+    // Without the sample the first pass leaves a key window at most 2^93
+    // wide.  With it, the estimated window and one widened retry may miss,
+    // leaving at most 2^94, which 16 refinements settle: 18 passes in all.
+    // Each refinement divides the width by 64.
+    // Without a host round trip (graph capture) all passes are launched;
+    // blocks whose locations have settled return at once.
     for (int pass = 0; pass < KNN_MAX_PASSES; ++pass) {
 #define LAGP_KNN_HIST(PP) hipLaunchKernelGGL(knn_hist_kernel<PP>, grid, dim3(KNN_THREADS), lds_hist, stream, \
-                                             D.Xsoa, D.N, D.p, XX, T, M, st, hist, chunk)
+                                             D.Xsoa, D.N, D.p, XX, T, M, st, hist, belowc, chunk)
         LAGP_DISPATCH_P(D.p, LAGP_KNN_HIST);
 #undef LAGP_KNN_HIST
         fill_u32(flags, 1, 0u, stream);
-        hipLaunchKernelGGL(knn_decide_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st,
-                           hist, T, M, M_per, bucket_max, flags);
+        hipLaunchKernelGGL(knn_decide_kernel, dim3(dgrid), dim3(256), 0, stream, st, hist, belowc, T, M, M_per, 1,
+                           bucket_max, fac, flags);
         if (!graph_safe) {
             uint32_t unsettled = 0;
             if (hipMemcpyAsync(&unsettled, flags, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||

@@ -53,6 +53,16 @@ __global__ void aos_to_soa_kernel(const double* __restrict__ aos, double* __rest
     soa[(int64_t)k * N + i] = aos[e];
 }
 
+// Rows 0, S, 2S, ... of the row-major design into a coordinate-major sample.
+__global__ void sample_soa_kernel(const double* __restrict__ aos, double* __restrict__ soa, int64_t Ns, int p, int S)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Ns * p) return;
+    int64_t j = e / p;
+    int k = (int)(e - j * p);
+    soa[(int64_t)k * Ns + j] = aos[j * S * p + k];
+}
+
 int ensure_ws(lagp_design* d, size_t bytes, hipStream_t stream)
 {
     if (bytes <= d->ws_bytes) return LAGP_OK;
@@ -128,7 +138,9 @@ int lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, u
     d->arch = d->arch.substr(0, d->arch.find(':'));
     d->max_lds = prop.sharedMemPerBlock;
     const size_t bytes = (size_t)N * p * sizeof(double);
+    const int64_t Ns = (N + lagp::KNN_SAMPLE_STRIDE - 1) / lagp::KNN_SAMPLE_STRIDE;
     if (hipMalloc(&d->Xaos, bytes) != hipSuccess || hipMalloc(&d->Xsoa, bytes) != hipSuccess ||
+        hipMalloc(&d->Xsoa_s, (size_t)Ns * p * sizeof(double)) != hipSuccess ||
         hipMalloc(&d->y, (size_t)N * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         lagp_design_destroy(d);
@@ -141,11 +153,15 @@ int lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, u
     const int64_t tot = N * p;
     hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d->Xaos,
                        d->Xsoa, N, p);
+    hipLaunchKernelGGL(sample_soa_kernel, dim3((unsigned)((Ns * p + 255) / 256)), dim3(256), 0, s, d->Xaos,
+                       d->Xsoa_s, Ns, p, lagp::KNN_SAMPLE_STRIDE);
     e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) { lagp_design_destroy(d); return hip_fail("design layout", e); }
     d->dev.Xaos = d->Xaos;
     d->dev.Xsoa = d->Xsoa;
+    d->dev.Xsoa_s = d->Xsoa_s;
+    d->dev.Ns = Ns;
     d->dev.y = d->y;
     d->dev.N = N;
     d->dev.p = p;
@@ -160,6 +176,7 @@ void lagp_design_destroy(lagp_design* d)
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
     if (d->Xaos) (void)hipFree(d->Xaos);
     if (d->Xsoa) (void)hipFree(d->Xsoa);
+    if (d->Xsoa_s) (void)hipFree(d->Xsoa_s);
     if (d->y) (void)hipFree(d->y);
     if (d->ws) (void)hipFree(d->ws);
     delete d;

@@ -29,7 +29,13 @@ struct DeviceDesign {
     const double* y = nullptr;     // N
     int64_t N = 0;
     int32_t p = 0;
+    // Every KNN_SAMPLE_STRIDE-th design row, p x Ns (the kNN estimates each
+    // location's candidate radius on it); nullptr when not built.
+    const double* Xsoa_s = nullptr;
+    int64_t Ns = 0;
 };
+
+constexpr int KNN_SAMPLE_STRIDE = 16;
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -91,6 +97,7 @@ struct DesignPlan {
     int rlds = 0;          // LDS-resident tile rows
     int rglob = 0;         // global-resident tile rows
     bool coords_lds = false;
+    bool y_lds = false;    // responses in LDS next to the coordinates
     int blocks = 0;        // persistent grid size
     size_t lds_bytes = 0;
     size_t lds_limit = 0;  // device LDS per workgroup

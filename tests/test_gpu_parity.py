@@ -84,6 +84,31 @@ def test_knn_ties_grid(lagp):
             assert np.array_equal(idx[t], ref), (M, t)
 
 
+@pytest.mark.parametrize("layout", ["far_sample", "near_sample", "duplicates"])
+def test_knn_unrepresentative_sample(lagp, layout):
+    """The kNN first estimates each location's candidate radius on every 16th
+    design row.  Designs whose sample misrepresents the rest (the estimate
+    misses low or high, or collapses to zero) must still give exact sets."""
+    r = np.random.default_rng(17)
+    N, p = 20000, 3
+    X = r.uniform(0.0, 1.0, (N, p))
+    if layout == "far_sample":
+        X[::16] += 5.0                      # the sample lies far from every location
+    elif layout == "near_sample":
+        X[1::16] += 5.0                     # ... and the rest in part far away
+        X[2::16] += 5.0
+        X[::16] = 0.5 + 0.01 * (X[::16] - 0.5)   # the sample packed near the centre
+    else:
+        X[::16] = X[0]                      # the sample is one repeated point
+    D = lagp.Design(X, np.zeros(N))
+    XX = np.concatenate([r.uniform(0.0, 1.0, (300, p)), X[:5]])
+    for M in (40, 700, 2000):
+        idx = _knn_gpu(D, XX, M)
+        for t in range(0, len(XX), 7):
+            ref, _ = oracle.knn(X, XX[t], M)
+            assert np.array_equal(idx[t], ref), (layout, M, t)
+
+
 # ------------------------------------------------------------- predict
 def test_predict_c0_full(c0):
     w, D = c0
