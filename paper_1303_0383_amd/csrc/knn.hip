@@ -196,6 +196,11 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
     // (a split holds fewer than 65536 design rows, so 16-bit counters suffice)
     const uint64_t lo_d = (uint64_t)(lo >> 31);
     const uint64_t hi_d = (uint64_t)((hi - 1) >> 31);
+    // Window bounds on whole squared-distance values (the index bits zero)
+    // and bins at least one distance unit wide: bins follow from the
+    // distance bits alone.
+    const u128 low31 = ((u128)1 << 31) - 1;
+    const bool aligned = ((lo & low31) == 0) && ((hi & low31) == 0) && shift >= 31;
 
     for (int64_t base = i0; base < i1; base += KNN_TILE) {
         const int count = (int)((i1 - base) < KNN_TILE ? (i1 - base) : KNN_TILE);
@@ -213,12 +218,19 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
             for (int ii = 0; ii < count; ++ii) {
                 double d2 = tile_d2<P>(tile + ii * p, x, p);
                 uint64_t bits = (uint64_t)__double_as_longlong(d2);
-                if (bits > hi_d) continue;
-                if (bits < lo_d) { nbelow += cbelow ? 1u : 0u; continue; }
-                u128 key = ((u128)bits << 31) | (uint64_t)(base + ii);
-                if (key < lo) { nbelow += cbelow ? 1u : 0u; continue; }
-                if (key >= hi) continue;
-                int b = (int)((key - lo) >> shift);
+                const bool under = bits < lo_d;
+                nbelow += (under && cbelow) ? 1u : 0u;
+                if (under || bits > hi_d) continue;
+                int b;
+                if (aligned) {
+                    // the window and its bins are whole distance values: 64-bit arithmetic
+                    b = (int)((bits - lo_d) >> (shift - 31));
+                } else {
+                    u128 key = ((u128)bits << 31) | (uint64_t)(base + ii);
+                    if (key < lo) { nbelow += cbelow ? 1u : 0u; continue; }
+                    if (key >= hi) continue;
+                    b = (int)((key - lo) >> shift);
+                }
                 h[b * KNN_THREADS + tid] += 1;
             }
         }
@@ -419,8 +431,11 @@ knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const doub
             uint64_t bits = (uint64_t)__double_as_longlong(d2);
             if (bits > hi_d) continue;
             const int64_t gi = base + ii;
-            u128 key = ((u128)bits << 31) | (uint64_t)gi;
-            if (bits < lo_d || key < lo) {
+            // the full key only at or above the window's first distance value
+            const bool under = bits < lo_d;
+            u128 key = 0;
+            if (!under) key = ((u128)bits << 31) | (uint64_t)gi;
+            if (under || key < lo) {
                 if (!split) {
                     out[nbelow++] = (int32_t)gi;
                 } else {
