@@ -200,6 +200,11 @@ def main() -> int:
         for line in open(traffic_file):
             if line.startswith("bytes_per_launch:"):
                 roofline["traffic"] = float(line.split(":")[1])
+        if roofline["traffic"]:
+            # measured HBM traffic per launch over this run's launch time: the
+            # rate at which the kernel streams its tile
+            roofline["traffic_rate_TBps"] = round(roofline["traffic"] / avg_launch_s / 1e12, 3)
+            roofline["traffic_frac_of_hbm_peak"] = round(roofline["traffic"] / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "locations/s", "n_gpus": 1,
