@@ -628,7 +628,7 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
             int num_cu, size_t max_lds, std::string* err, bool graph_safe)
 {
     if (T == 0) return 0;
-    const int32_t bucket_max = 512;
+    const int32_t bucket_max = KNN_BUCKET_MAX;
     if (ws_bytes < knn_workspace_bytes(T, bucket_max)) { *err = "knn workspace too small"; return -1; }
     char* w = (char*)ws;
     KnnState* st = (KnnState*)w; w += align256((size_t)T * sizeof(KnnState));

@@ -90,8 +90,6 @@ int check_device(const lagp_design* d)
     return LAGP_OK;
 }
 
-const int32_t kBucketMax = 512;
-
 }  // namespace lagp_rt
 
 using namespace lagp_rt;
@@ -198,7 +196,7 @@ int lagp_knn(const lagp_design* design, const double* XX, int64_t T, int32_t M, 
     hipStream_t s = (hipStream_t)stream;
     for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
         const int64_t tc = std::min(kChunk, T - t0);
-        rc = ensure_ws(d, lagp::knn_workspace_bytes(tc, kBucketMax), s);
+        rc = ensure_ws(d, lagp::knn_workspace_bytes(tc, lagp::KNN_BUCKET_MAX), s);
         if (rc) return rc;
         std::string err;
         int r = lagp::knn_run(d->dev, XX + t0 * d->dev.p, tc, M, nullptr, idx + t0 * idx_stride, idx_stride, true,
@@ -405,7 +403,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
         }
         P->chunks.push_back(c);
     }
-    P->knn_b = lagp::align256(lagp::knn_workspace_bytes(tc_max, kBucketMax));
+    P->knn_b = lagp::align256(lagp::knn_workspace_bytes(tc_max, lagp::KNN_BUCKET_MAX));
     P->cand_b = lagp::align256((size_t)tc_max * Mmax * sizeof(int32_t));
     P->design_b = lagp::align256(design_b);
     P->order_b = P->uneven ? lagp::align256((size_t)T * sizeof(int32_t)) : 0;

@@ -36,6 +36,8 @@ struct DeviceDesign {
 };
 
 constexpr int KNN_SAMPLE_STRIDE = 16;
+// Keys a location's final kNN window may hold (sorted in LDS by one block).
+constexpr int32_t KNN_BUCKET_MAX = 512;
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
