@@ -63,9 +63,12 @@ def _configure(L):
     L.lagp_oracle_local.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, P, P]
     L.lagp_oracle_batch.argtypes = [P, P, i64, i32, P, i64, i32, i32, i64, P, P, f64, f64,
                                     P, i64, P, P, i32]
+    L.lagp_oracle_loglik.argtypes = [P, P, i32, P, i32, f64, f64, P]
+    L.lagp_oracle_mle.argtypes = [P, P, i32, P, i32, f64, f64, f64, f64, i32, f64, P, P]
+    L.lagp_oracle_alc2.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, f64, f64, i32, f64, P, P, P, P]
     for f in (L.lagp_oracle_knn, L.lagp_oracle_predict, L.lagp_oracle_alc,
               L.lagp_oracle_alc_brute, L.lagp_oracle_local, L.lagp_oracle_batch,
-              L.lagp_oracle_max_threads):
+              L.lagp_oracle_max_threads, L.lagp_oracle_loglik, L.lagp_oracle_mle, L.lagp_oracle_alc2):
         f.restype = C.c_int
 
 
@@ -151,6 +154,43 @@ def batch(X, y, XX, n0, n, M, d, g, n_per=None, M_per=None, threads=0, L=None):
     if rc < 0:
         raise ValueError(f"oracle batch failed: {rc}")
     return st, sel, out
+
+
+# Newton controls shared by the MLE functions (a reading: the paper leaves them open).
+MLE_MAXIT = 100
+MLE_TOL = 1e-10
+
+
+def loglik(X, y, D, d, g, L=None):
+    """(l, l', l'') of the local design D at lengthscale d (eqs gpk, dl, d2l)."""
+    X = _f64(X); y = _f64(y); D = _i32(D)
+    out = np.empty(3)
+    rc = (L or lib()).lagp_oracle_loglik(_ptr(X), _ptr(y), X.shape[1], _ptr(D), len(D), d, g, _ptr(out))
+    if rc < 0:
+        raise ValueError(f"oracle loglik failed: {rc}")
+    return rc, out
+
+
+def mle(X, y, D, d0, g, tmin, tmax, maxit=MLE_MAXIT, tol=MLE_TOL, L=None):
+    """(rc, theta_hat, iterations) by Newton's method from d0."""
+    X = _f64(X); y = _f64(y); D = _i32(D)
+    th = np.empty(1); it = np.empty(1, np.int32)
+    rc = (L or lib()).lagp_oracle_mle(_ptr(X), _ptr(y), X.shape[1], _ptr(D), len(D), d0, g, tmin, tmax,
+                                      maxit, tol, _ptr(th), _ptr(it))
+    if rc < 0:
+        raise ValueError(f"oracle mle failed: {rc}")
+    return rc, float(th[0]), int(it[0])
+
+
+def alc2(X, y, x, n0, n, M, d0, g, tmin, tmax, maxit=MLE_MAXIT, tol=MLE_TOL, L=None):
+    """Two-stage scheme: (rc, sel1, sel2, (theta1, theta2), out[5])."""
+    X = _f64(X); y = _f64(y); x = _f64(x)
+    s1 = np.empty(n, np.int32); s2 = np.empty(n, np.int32); th = np.empty(2); out = np.empty(5)
+    rc = (L or lib()).lagp_oracle_alc2(_ptr(X), _ptr(y), X.shape[0], X.shape[1], _ptr(x), n0, n, M, d0, g,
+                                       tmin, tmax, maxit, tol, _ptr(s1), _ptr(s2), _ptr(th), _ptr(out))
+    if rc < 0:
+        raise ValueError(f"oracle alc2 failed: {rc}")
+    return rc, s1, s2, (float(th[0]), float(th[1])), out
 
 
 def max_threads() -> int:

@@ -33,6 +33,15 @@
  * s2 = psi * v_n(x) / n with psi = Y'K^{-1}Y, df = n, variance
  * V = s2 * n / (n-2) = psi * v_n(x) / (n-2).
  *
+ * Local lengthscale inference (SM Section 3, Sections 3.1 and 4.1): the
+ * concentrated log likelihood of a local design (eq gpk, constants dropped)
+ *   l(theta) = -1/2 log|K| - n/2 log psi,   psi = Y'K^{-1}Y,
+ * its first and second derivatives in theta (eqs dl and d2l, with the
+ * entrywise derivatives of K for the isotropic Gaussian kernel), a Newton
+ * search for its maximum inside (tmin, tmax), and the two-stage scheme of
+ * Section 4.1 with one repetition.  Every evaluation forms K^{-1} explicitly
+ * from a fresh Cholesky factor.
+ *
  * Readings where the paper is silent (each is listed in the design notes):
  * distances are summed over coordinates left to right with no fused
  * multiply-add; nearest neighbours are ordered by (squared distance, index);
@@ -398,6 +407,160 @@ int lagp_oracle_batch(const double *X, const double *y, int64_t N, int32_t p, co
     }
     (void)nthreads;
     return err;
+}
+
+/* ---- local lengthscale inference (Section 3.1, last paragraph of Section
+ * 4.1's two-stage scheme; derivatives from SM Section 3, eqs dl and d2l).
+ *
+ * For the local design D (n indices) and lengthscale theta, with
+ * K = K(D,D) + eta I, psi = Y'K^{-1}Y, the log marginal likelihood of eq gpk
+ * (N -> n, dropping the theta-free constant) is
+ *   l(theta) = -1/2 log|K| - n/2 log psi,
+ * and with Kd = dK/dtheta, Kdd = d2K/dtheta2 (zero on the diagonal, whose
+ * entries 1 + eta do not depend on theta; off the diagonal
+ * dK/dtheta = K d^2/theta^2 and d2K/dtheta2 = K (d^4/theta^4 - 2 d^2/theta^3)):
+ *   l'  = -1/2 tr(K^{-1} Kd) + n/2 Y'K^{-1}Kd K^{-1}Y / psi                 (eq dl)
+ *   l'' = -1/2 tr(K^{-1} (Kdd - Kd K^{-1} Kd))
+ *         + n/(2 psi) Y'K^{-1} (Kdd - 2 Kd K^{-1} Kd) K^{-1}Y
+ *         + n/(2 psi^2) (Y'K^{-1}Kd K^{-1}Y)^2                             (eq d2l)
+ * computed here from the explicit inverse K^{-1} = L^{-T} L^{-1}.
+ * out3 = {l, l', l''}. */
+int lagp_oracle_loglik(const double *X, const double *y, int32_t p, const int32_t *D, int32_t n,
+                       double theta, double eta, double *out3)
+{
+    if (n < 1 || !(theta > 0.0)) return ORACLE_EINVAL;
+    const size_t nn = (size_t)n * n;
+    double *K = (double *)malloc(nn * sizeof(double));
+    double *L = (double *)malloc(nn * sizeof(double));
+    double *Li = (double *)calloc(nn, sizeof(double));
+    double *Ki = (double *)malloc(nn * sizeof(double));
+    double *Kd = (double *)malloc(nn * sizeof(double));
+    double *Kdd = (double *)malloc(nn * sizeof(double));
+    double *B = (double *)malloc(nn * sizeof(double));
+    double *e = (double *)malloc((size_t)n * sizeof(double));
+    double *col = (double *)malloc((size_t)n * sizeof(double));
+    double *Yd = (double *)malloc((size_t)n * sizeof(double));
+    double *w = (double *)malloc((size_t)n * sizeof(double));
+    double *v = (double *)malloc((size_t)n * sizeof(double));
+    double *z = (double *)malloc((size_t)n * sizeof(double));
+    int rc = ORACLE_OK;
+    if (!K || !L || !Li || !Ki || !Kd || !Kdd || !B || !e || !col || !Yd || !w || !v || !z) {
+        rc = ORACLE_ENOMEM;
+        goto done;
+    }
+    design_cov(X, p, D, n, theta, eta, K);
+    for (int a = 0; a < n; a++) {
+        Yd[a] = y[D[a]];
+        for (int b = 0; b < n; b++) {
+            if (a == b) {
+                Kd[(size_t)a * n + b] = 0.0;
+                Kdd[(size_t)a * n + b] = 0.0;
+            } else {
+                const double d2 = sqdist(X + (size_t)D[a] * p, X + (size_t)D[b] * p, p);
+                const double k = K[(size_t)a * n + b];
+                Kd[(size_t)a * n + b] = k * d2 / (theta * theta);
+                Kdd[(size_t)a * n + b] = k * (d2 * d2 / (theta * theta * theta * theta) - 2.0 * d2 / (theta * theta * theta));
+            }
+        }
+    }
+    if (cholesky(K, n, L) != 0) { rc = ORACLE_NOTPD; goto done; }
+    /* L^{-1} column by column, then K^{-1} = L^{-T} L^{-1}. */
+    for (int c = 0; c < n; c++) {
+        for (int a = 0; a < n; a++) e[a] = (a == c) ? 1.0 : 0.0;
+        forward_solve(L, n, e, col);
+        for (int a = 0; a < n; a++) Li[(size_t)a * n + c] = col[a];
+    }
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) {
+            double s = 0.0;
+            for (int k = 0; k < n; k++) s += Li[(size_t)k * n + a] * Li[(size_t)k * n + b];
+            Ki[(size_t)a * n + b] = s;
+        }
+    for (int a = 0; a < n; a++) w[a] = dot(Ki + (size_t)a * n, Yd, n);   /* K^{-1} Y */
+    {
+        double logdet = 0.0;
+        for (int a = 0; a < n; a++) logdet += 2.0 * log(L[(size_t)a * n + a]);
+        const double psi = dot(Yd, w, n);
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++) {
+                t1 += Ki[(size_t)a * n + b] * Kd[(size_t)b * n + a];
+                t2 += Ki[(size_t)a * n + b] * Kdd[(size_t)b * n + a];
+                double s = 0.0;
+                for (int k = 0; k < n; k++) s += Ki[(size_t)a * n + k] * Kd[(size_t)k * n + b];
+                B[(size_t)a * n + b] = s;                                     /* K^{-1} Kd */
+            }
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++) t3 += B[(size_t)a * n + b] * B[(size_t)b * n + a];
+        for (int a = 0; a < n; a++) v[a] = dot(Kd + (size_t)a * n, w, n);     /* Kd K^{-1} Y */
+        for (int a = 0; a < n; a++) z[a] = dot(Kdd + (size_t)a * n, w, n);    /* Kdd K^{-1} Y */
+        const double q = dot(w, v, n);
+        const double r = dot(w, z, n);
+        for (int a = 0; a < n; a++) e[a] = dot(Ki + (size_t)a * n, v, n);     /* K^{-1} Kd K^{-1} Y */
+        const double sq = dot(v, e, n);
+        out3[0] = -0.5 * logdet - 0.5 * n * log(psi);
+        out3[1] = -0.5 * t1 + 0.5 * n * q / psi;
+        out3[2] = -0.5 * (t2 - t3) + 0.5 * n * (r - 2.0 * sq) / psi + 0.5 * n * q * q / (psi * psi);
+    }
+done:
+    free(K); free(L); free(Li); free(Ki); free(Kd); free(Kdd); free(B); free(e); free(col);
+    free(Yd); free(w); free(v); free(z);
+    return rc;
+}
+
+/* Maximum-likelihood lengthscale for the local design D by Newton's method
+ * on l(theta) (the paper asks for a Newton-like method with the analytic
+ * derivatives and leaves the details open).  From theta0 (or sqrt(tmin tmax)
+ * when theta0 is outside (tmin, tmax)): where l'' < 0 the step is -l'/l''; elsewhere it is theta
+ * in the direction of l' (doubling or zeroing theta).  A step that would
+ * leave (tmin, tmax) goes half way to the bound instead.  Iteration stops
+ * when a step moves theta by at most tol * theta, or after maxit steps.
+ * Returns the final theta in *theta_hat and the step count in *iters. */
+int lagp_oracle_mle(const double *X, const double *y, int32_t p, const int32_t *D, int32_t n,
+                    double theta0, double eta, double tmin, double tmax, int32_t maxit, double tol,
+                    double *theta_hat, int32_t *iters)
+{
+    if (n < 2 || !(tmin > 0.0) || !(tmax > tmin) || maxit < 1 || !(tol > 0.0)) return ORACLE_EINVAL;
+    double theta = (theta0 > tmin && theta0 < tmax) ? theta0 : sqrt(tmin * tmax);
+    int it = 0, rc = ORACLE_OK;
+    while (it < maxit) {
+        double l[3];
+        rc = lagp_oracle_loglik(X, y, p, D, n, theta, eta, l);
+        if (rc != ORACLE_OK) break;
+        ++it;
+        const double step = (l[2] < 0.0) ? -l[1] / l[2] : (l[1] > 0.0 ? theta : -theta);
+        double next = theta + step;
+        if (!(next > tmin)) next = 0.5 * (theta + tmin);
+        if (!(next < tmax)) next = 0.5 * (theta + tmax);
+        const int done = fabs(next - theta) <= tol * theta;
+        theta = next;
+        if (done) break;
+    }
+    *theta_hat = theta;
+    *iters = it;
+    return rc;
+}
+
+/* The two-stage scheme of Section 4.1 with one repetition (the paper's
+ * "alc2"): designs at theta0, the local MLE theta1 from them, designs again
+ * at theta1, the local MLE theta2 from those, and the prediction from the
+ * second designs at theta2.  thetas = {theta1, theta2}; sel1, sel2 receive
+ * the two designs; out5 as in lagp_oracle_local. */
+int lagp_oracle_alc2(const double *X, const double *y, int64_t N, int32_t p, const double *x, int32_t n0,
+                     int32_t n, int64_t M, double theta0, double eta, double tmin, double tmax,
+                     int32_t maxit, double tol, int32_t *sel1, int32_t *sel2, double *thetas, double *out5)
+{
+    double o[5];
+    int32_t its;
+    int rc = lagp_oracle_local(X, y, N, p, x, n0, n, M, theta0, eta, NULL, sel1, o, NULL);
+    if (rc != ORACLE_OK) return rc;
+    rc = lagp_oracle_mle(X, y, p, sel1, n, theta0, eta, tmin, tmax, maxit, tol, &thetas[0], &its);
+    if (rc != ORACLE_OK) return rc;
+    rc = lagp_oracle_local(X, y, N, p, x, n0, n, M, thetas[0], eta, NULL, sel2, o, NULL);
+    if (rc != ORACLE_OK) return rc;
+    rc = lagp_oracle_mle(X, y, p, sel2, n, thetas[0], eta, tmin, tmax, maxit, tol, &thetas[1], &its);
+    if (rc != ORACLE_OK) return rc;
+    return lagp_oracle_predict(X, y, p, x, sel2, n, thetas[1], eta, out5);
 }
 
 int lagp_oracle_max_threads(void)
