@@ -79,6 +79,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_n50", choices=["c2_n50", "c2", "c1", "c0", "c3", "c4"])
     ap.add_argument("--T", type=int, default=None, help="use only the first T locations")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--method", default="alc", choices=["alc", "alc2"],
+                    help="alc: designs at the fixed lengthscale; alc2: the two-stage scheme with local MLEs")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="locations in the CPU oracle sample (0: skip)")
     ap.add_argument("--parity-sample", type=int, default=64, help="sampled locations checked against the oracle")
     ap.add_argument("--graph", default="auto", choices=["auto", "on", "off"],
@@ -129,10 +131,21 @@ def main() -> int:
                           sel=torch.empty((T, nmax), dtype=torch.int32, device=dev),
                           status=torch.empty(T, dtype=torch.int8, device=dev))
 
-    use_graph = args.graph == "on" or (args.graph == "auto" and w.n_per is not None)
+    alc2 = args.method == "alc2"
+    # graphs capture fixed-shape batches of the one-stage scheme
+    use_graph = not alc2 and (args.graph == "on" or (args.graph == "auto" and w.n_per is not None))
+    if alc2:
+        import workloads
+        tmin, tmax = workloads.mle_range(w.X)
+        out.theta1 = torch.empty(T, dtype=torch.float64, device=dev)
+        out.theta2 = torch.empty(T, dtype=torch.float64, device=dev)
 
     def eager_step():
-        D.predict(XX, w.n0, nmax, Mmax, w.d, w.g, n_per=n_per, ncand_per=M_per, precision=prec, out=out)
+        if alc2:
+            D.predict_alc2(XX, w.n0, nmax, Mmax, w.d, w.g, tmin, tmax, n_per=n_per, ncand_per=M_per,
+                           precision=prec, out=out)
+        else:
+            D.predict(XX, w.n0, nmax, Mmax, w.d, w.g, n_per=n_per, ncand_per=M_per, precision=prec, out=out)
 
     if use_graph:
         # The batch plan (buckets, work lists, kernel variants, workspace) is
@@ -167,13 +180,14 @@ def main() -> int:
         lagp.lagp_phase_times(D.handle)
         eager_step()
         torch.cuda.synchronize()
-        knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+        phase, launches = lagp.lagp_phase_times(D.handle)
         lagp.lagp_timing_enable(D.handle, False)
-        knn_ms, des_ms = knn_ms * args.steps, des_ms * args.steps
+        phase = {k: v * args.steps for k, v in phase.items()}
         launches *= args.steps
     else:
-        knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+        phase, launches = lagp.lagp_phase_times(D.handle)
         lagp.lagp_timing_enable(D.handle, False)
+    des_ms = phase["design"]
 
     value = T * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
@@ -186,6 +200,8 @@ def main() -> int:
     else:
         flops = T * design_flops(w.n, w.ncand, w.p, w.n0)
         exps = T * design_exps(w.n, w.ncand)
+    passes = 2 if alc2 else 1   # design passes per step
+    flops, exps = passes * flops, passes * exps
     launches_per_step = max(1, launches // args.steps)
     per_launch_flops = flops / launches_per_step
     avg_launch_s = des_ms / max(launches, 1) / 1e3
@@ -211,9 +227,9 @@ def main() -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32-tile", "data": "synthetic",
-        "config": {"workload": args.workload, "N": w.N, "p": w.p, "T": T, "n0": w.n0, "n": nmax,
-                   "ncand": Mmax, "d": w.d, "g": w.g, "uneven": w.n_per is not None, "graph": use_graph},
-        "phase_ms_per_step": {"knn": round(knn_ms / args.steps, 3), "design": round(des_ms / args.steps, 3)},
+        "config": {"workload": args.workload, "method": args.method, "N": w.N, "p": w.p, "T": T, "n0": w.n0,
+                   "n": nmax, "ncand": Mmax, "d": w.d, "g": w.g, "uneven": w.n_per is not None, "graph": use_graph},
+        "phase_ms_per_step": {k: round(v / args.steps, 3) for k, v in phase.items() if v > 0 or k in ("knn", "design")},
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),
         "roofline": roofline,
@@ -240,6 +256,42 @@ def main() -> int:
         except AssertionError as e:
             m = {"ok": False, "error": str(e)}
         result["parity"] = {"locations": len(idx), "kind": "mixed", **m}
+    elif args.parity_sample > 0 and alc2:
+        # Stage by stage on a sample, each stage fed the GPU's previous one:
+        # the second designs against the oracle's at the GPU's theta1, theta2
+        # against the oracle's MLE of those designs, the prediction against
+        # the oracle's from them at the GPU's theta2.
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import oracle
+        from parity import compare
+        idx = np.sort(rng.choice(T, min(args.parity_sample, T), replace=False))
+        th1, th2 = out.theta1.cpu().numpy(), out.theta2.cpu().numpy()
+        try:
+            worst_th = worst_mu = 0.0
+            for t in idx:
+                nt = int(w.n_per[t]) if w.n_per is not None else w.n
+                s2_ = res["sel"][t, :nt]
+                rc, tho, _ = oracle.mle(w.X, w.y, s2_, th1[t], w.g, tmin, tmax)
+                worst_th = max(worst_th, abs(th2[t] - tho) / tho)
+                rc, o = oracle.predict(w.X, w.y, w.XX[t], s2_, th2[t], w.g)
+                worst_mu = max(worst_mu, abs(res["mean"][t] - o[0]) / max(abs(o[0]), float(np.std(w.y))))
+            ti = torch.as_tensor(idx, device=dev)
+            nps = None if w.n_per is None else w.n_per[idx]
+            mps = None if w.ncand_per is None else w.ncand_per[idx]
+            d1 = D.predict(XX[ti], w.n0, nmax, Mmax, w.d, w.g, d_per=out.theta1[ti],
+                           n_per=None if nps is None else n_per[ti], ncand_per=None if mps is None else M_per[ti])
+            torch.cuda.synchronize()
+            r1 = {k: getattr(d1, k).cpu().numpy() for k in ("mean", "s2", "df", "var", "sel", "status")}
+            nts = [int(nps[i]) if nps is not None else w.n for i in range(len(idx))]
+            same = all(np.array_equal(r1["sel"][i, :nts[i]], res["sel"][t, :nts[i]]) for i, t in enumerate(idx))
+            summ = compare(w.X, w.y, w.XX[idx], w.n0, w.n, w.ncand, th1[idx], w.g, r1, n_per=nps, M_per=mps)
+            ok = same and worst_th <= 1e-8 and worst_mu <= 1e-9
+            result["parity"] = {"locations": len(idx), "ok": ok, "kind": "stagewise",
+                                "theta2_rel": float(f"{worst_th:.3e}"), "mean_rel": float(f"{worst_mu:.3e}"),
+                                "second_designs": {k: (float(f"{v:.3e}") if isinstance(v, float) else v)
+                                                   for k, v in summ.items()}}
+        except AssertionError as e:
+            result["parity"] = {"locations": len(idx), "ok": False, "error": str(e)}
     elif args.parity_sample > 0:
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from parity import compare
@@ -259,8 +311,18 @@ def main() -> int:
         idx = np.sort(rng.choice(T, min(args.cpu_sample, T), replace=False))
         sub = w.subset(idx)
         tc = time.perf_counter()
-        oracle.batch(sub.X, sub.y, sub.XX, sub.n0, sub.n, sub.ncand, sub.d, sub.g, n_per=sub.n_per,
-                     M_per=sub.ncand_per, threads=threads)
+        if alc2:
+            # the oracle's two-stage function is per location: a thread pool over
+            # the sample (the ctypes calls release the interpreter lock)
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(lambda t: oracle.alc2(sub.X, sub.y, sub.XX[t], sub.n0,
+                                                  int(sub.n_per[t]) if sub.n_per is not None else sub.n,
+                                                  int(sub.ncand_per[t]) if sub.ncand_per is not None else sub.ncand,
+                                                  sub.d, sub.g, tmin, tmax), range(len(idx))))
+        else:
+            oracle.batch(sub.X, sub.y, sub.XX, sub.n0, sub.n, sub.ncand, sub.d, sub.g, n_per=sub.n_per,
+                         M_per=sub.ncand_per, threads=threads)
         cpu_s = time.perf_counter() - tc
         result["cpu_baseline"] = {"value": round(len(idx) / cpu_s, 2), "unit": "locations/s", "cores": threads,
                                   "kind": "oracle",

@@ -124,16 +124,74 @@ int lagp_predict(const lagp_design *design, const double *XX, int64_t T, const l
                  int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
                  void *stream);
 
+/* lagp_predict with a lengthscale per location (Section 4.2: after local
+ * inference each location has its own theta_x, possibly smoothed over the
+ * locations): d_per is a device double[T] that replaces params->d, which must
+ * still be a valid lengthscale.  A location whose d_per entry is not a
+ * positive finite number gets status LAGP_LOC_NOTPD, NaN outputs and sel
+ * entries -1. */
+int lagp_predict_theta(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
+                       const double *d_per, const int32_t *n_per, const int32_t *ncand_per, double *mean,
+                       double *s2, int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
+                       void *stream);
+
 /* Local GP prediction from given local designs (eqs predgp, preds2 with
  * N -> n): for each location t, K_n = K(D_t, D_t) + g I over the n (or n_per[t])
  * design indices sel[t * sel_stride + 0 .. n-1] is factorised afresh in FP64
- * and mean, s2, df, var written as in lagp_predict.  A location with an index
- * outside [0, N) or a non-positive pivot gets status LAGP_LOC_NOTPD and NaN
+ * and mean, s2, df, var written as in lagp_predict.  d_per (nullable, device
+ * double[T]) gives each location its own lengthscale in place of d.  A
+ * location with an index outside [0, N), a lengthscale that is not a positive
+ * finite number, or a non-positive pivot gets status LAGP_LOC_NOTPD and NaN
  * outputs.  Device pointers; n is limited by LDS (about 190 on gfx950). */
 int lagp_predict_designs(const lagp_design *design, const double *XX, int64_t T, const int32_t *sel,
-                         int64_t sel_stride, const int32_t *n_per, int32_t n, double d, double g,
-                         double *mean, double *s2, int32_t *df, double *var, int8_t *status,
+                         int64_t sel_stride, const int32_t *n_per, int32_t n, double d, const double *d_per,
+                         double g, double *mean, double *s2, int32_t *df, double *var, int8_t *status,
                          void *stream);
+
+/* ---- Local inference of the lengthscale (Sections 3.2 and 4.2).
+ *
+ * The concentrated log likelihood of a local design (eq gpk of Section 2,
+ * constants dropped) l(theta) = -1/2 log|K| - n/2 log(Y'K^{-1}Y), with
+ * K = K(D, D) + g I, is maximised over theta by Newton's method with its
+ * analytic first and second derivatives (eqs dl, d2l of SM Section 2).  The
+ * paper leaves the controls of the search open; these are the ones taken: where l'' < 0 the step is -l'/l'', elsewhere
+ * it is theta in the direction of l'; a step that would leave (tmin, tmax)
+ * goes half way to the bound instead; the search starts from theta0 (from
+ * sqrt(tmin tmax) when theta0 is outside the interval) and stops when a step
+ * moves theta by at most tol * theta, or after maxit iterates. */
+typedef struct {
+    double tmin, tmax;  /* search interval, 0 < tmin < tmax, finite          */
+    int32_t maxit;      /* Newton iterates, >= 1 (100 is ample)               */
+    double tol;         /* relative step that ends the search, > 0 (1e-10)    */
+} lagp_mle_params;
+
+/* Maximum-likelihood lengthscale of T given local designs.
+ *   sel       device int32 T x sel_stride design indices (first n, or n_per[t]);
+ *   n_per     optional device int32[T] per-location design size (else n);
+ *   d0_per    optional device double[T] starting lengthscales (else d0);
+ *   d_hat     device double[T] estimates;
+ *   iters     optional device int32[T] Newton iterates taken;
+ *   status    optional device int8[T]: LAGP_LOC_NOTPD where a design index is
+ *             outside [0, N), the design has fewer than 2 points, or K was
+ *             not positive definite at some iterate (d_hat is then NaN).
+ * The designs are held in LDS: n up to about 128 on gfx950 (p = 8). */
+int lagp_mle(const lagp_design *design, int64_t T, const int32_t *sel, int64_t sel_stride, const int32_t *n_per,
+             int32_t n, const double *d0_per, double d0, double g, const lagp_mle_params *mle, double *d_hat,
+             int32_t *iters, int8_t *status, void *stream);
+
+/* The two-stage scheme of Section 4.2 with one repetition ("alc2"), on the
+ * device end to end: greedy ALC designs at params->d (or d_per), the local
+ * MLE theta1 of each design, designs again at theta1, the local MLE theta2 of
+ * the new designs (Newton started from theta1), and the prediction from the
+ * second designs at theta2.  The candidate sets are computed once.  Outputs
+ * as in lagp_predict, sel holding the second designs; d1 and d2 (optional
+ * device double[T]) receive theta1 and theta2.  A location that fails at any
+ * stage gets status LAGP_LOC_NOTPD and NaN outputs.  Requires n >= 2 for every
+ * location; the mixed precision mode applies to both design passes. */
+int lagp_predict_alc2(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
+                      const lagp_mle_params *mle, const double *d_per, const int32_t *n_per,
+                      const int32_t *ncand_per, double *mean, double *s2, int32_t *df, double *var, int32_t *sel,
+                      int64_t sel_stride, int8_t *status, double *d1, double *d2, void *stream);
 
 /* ---- Fixed-shape batches (uneven sizes, HIP-graph replay).
  *
@@ -231,15 +289,18 @@ double lagp_monotonic_seconds(void);
 int lagp_workspace_bytes(const lagp_design *design, int64_t T, int32_t nmax, int32_t ncand_max,
                          size_t *out);
 
-/* Per-phase device timing.  While enabled, lagp_predict records HIP events on
- * its stream around the two phases of each chunk of locations: the
- * candidate-set (kNN) kernels, then the greedy-design kernel launches (one
- * per size bucket, plus in the mixed mode the FP64 prediction kernel and the
- * FP64 redo launch).  lagp_phase_times waits for the recorded events, returns
- * the summed milliseconds and the number of design-kernel bucket launches
+/* Per-phase device timing.  While enabled, the prediction entry points record
+ * HIP events on their stream between the phases of each chunk of locations:
+ * the candidate-set (kNN) kernels; each design pass (the greedy-design kernel
+ * launches, one per size bucket, plus in the mixed mode the FP64 prediction
+ * kernel and the FP64 redo launch); in the two-stage scheme each likelihood
+ * pass and the final prediction.  lagp_phase_times waits for the recorded
+ * events, writes the summed milliseconds per phase into ms[LAGP_PHASES]
+ * (indexed by LAGP_PHASE_*) and the number of design-kernel bucket launches
  * since the last call, and clears the record. */
+enum { LAGP_PHASE_KNN = 0, LAGP_PHASE_DESIGN = 1, LAGP_PHASE_MLE = 2, LAGP_PHASE_PREDICT = 3, LAGP_PHASES = 4 };
 int lagp_timing_enable(lagp_design *design, int enable);
-int lagp_phase_times(lagp_design *design, double *knn_ms, double *design_ms, int64_t *design_launches);
+int lagp_phase_times(lagp_design *design, double *ms, int64_t *design_launches);
 
 /* Number of HIP devices visible (0 when none); never fails. */
 int lagp_device_count(void);

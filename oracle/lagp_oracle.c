@@ -33,13 +33,13 @@
  * s2 = psi * v_n(x) / n with psi = Y'K^{-1}Y, df = n, variance
  * V = s2 * n / (n-2) = psi * v_n(x) / (n-2).
  *
- * Local lengthscale inference (SM Section 3, Sections 3.1 and 4.1): the
- * concentrated log likelihood of a local design (eq gpk, constants dropped)
+ * Local lengthscale inference (Sections 3.2 and 4.2): the concentrated log
+ * likelihood of a local design (eq gpk of Section 2, constants dropped)
  *   l(theta) = -1/2 log|K| - n/2 log psi,   psi = Y'K^{-1}Y,
- * its first and second derivatives in theta (eqs dl and d2l, with the
- * entrywise derivatives of K for the isotropic Gaussian kernel), a Newton
+ * its first and second derivatives in theta (eqs dl and d2l of SM Section 2,
+ * with the entrywise derivatives of K for the isotropic Gaussian kernel), a Newton
  * search for its maximum inside (tmin, tmax), and the two-stage scheme of
- * Section 4.1 with one repetition.  Every evaluation forms K^{-1} explicitly
+ * Section 4.2 with one repetition.  Every evaluation forms K^{-1} explicitly
  * from a fresh Cholesky factor.
  *
  * Readings where the paper is silent (each is listed in the design notes):
@@ -409,8 +409,8 @@ int lagp_oracle_batch(const double *X, const double *y, int64_t N, int32_t p, co
     return err;
 }
 
-/* ---- local lengthscale inference (Section 3.1, last paragraph of Section
- * 4.1's two-stage scheme; derivatives from SM Section 3, eqs dl and d2l).
+/* ---- local lengthscale inference (Section 3.2, last paragraph, and the
+ * two-stage scheme of Section 4.2; derivatives from SM Section 2, eqs dl and d2l).
  *
  * For the local design D (n indices) and lengthscale theta, with
  * K = K(D,D) + eta I, psi = Y'K^{-1}Y, the log marginal likelihood of eq gpk
@@ -541,7 +541,7 @@ int lagp_oracle_mle(const double *X, const double *y, int32_t p, const int32_t *
     return rc;
 }
 
-/* The two-stage scheme of Section 4.1 with one repetition (the paper's
+/* The two-stage scheme of Section 4.2 with one repetition (the paper's
  * "alc2"): designs at theta0, the local MLE theta1 from them, designs again
  * at theta1, the local MLE theta2 from those, and the prediction from the
  * second designs at theta2.  thetas = {theta1, theta2}; sel1, sel2 receive

@@ -24,6 +24,7 @@ LAGP_LOC_OK, LAGP_LOC_NOTPD = 0, 1
 LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32 = 0, 1
 LAGP_PTR_HOST, LAGP_STRICT = 1, 2
 LAGP_BATCH_SEL, LAGP_BATCH_STATUS = 1, 2
+PHASES = ("knn", "design", "mle", "predict")   # LAGP_PHASE_* order
 
 # torch first: its bundled HIP runtime is then the one the library binds to.
 # Loading the library first would map a second HIP runtime into the process.
@@ -41,6 +42,10 @@ class lagp_params(C.Structure):
                 ("g", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32)]
 
 
+class lagp_mle_params(C.Structure):
+    _fields_ = [("tmin", C.c_double), ("tmax", C.c_double), ("maxit", C.c_int32), ("tol", C.c_double)]
+
+
 _P = C.c_void_p
 _lib.lagp_design_create.argtypes = [_P, _P, C.c_int64, C.c_int32, C.c_uint32, _P, C.POINTER(_P)]
 _lib.lagp_design_destroy.argtypes = [_P]
@@ -48,11 +53,17 @@ _lib.lagp_design_destroy.restype = None
 _lib.lagp_knn.argtypes = [_P, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]
 _lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P,
                               C.c_int64, _P, _P]
-_lib.lagp_predict_designs.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int32, C.c_double, C.c_double,
+_lib.lagp_predict_theta.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P, _P,
+                                   C.c_int64, _P, _P]
+_lib.lagp_predict_alc2.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_mle_params), _P, _P, _P,
+                                  _P, _P, _P, _P, _P, C.c_int64, _P, _P, _P, _P]
+_lib.lagp_mle.argtypes = [_P, C.c_int64, _P, C.c_int64, _P, C.c_int32, _P, C.c_double, C.c_double,
+                         C.POINTER(lagp_mle_params), _P, _P, _P, _P]
+_lib.lagp_predict_designs.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int32, C.c_double, _P, C.c_double,
                                       _P, _P, _P, _P, _P, _P]
 _lib.lagp_workspace_bytes.argtypes = [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
 _lib.lagp_timing_enable.argtypes = [_P, C.c_int]
-_lib.lagp_phase_times.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+_lib.lagp_phase_times.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.lagp_batch_create.argtypes = [_P, C.c_int64, C.POINTER(lagp_params), _P, _P, C.c_uint32, C.POINTER(_P)]
 _lib.lagp_batch_enqueue.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.c_int64, _P, _P]
 _lib.lagp_batch_launch_graph.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.c_int64, _P, _P]
@@ -72,7 +83,8 @@ _lib.lagp_last_error.restype = C.c_char_p
 for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
            "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
            "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant",
-           "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats"):
+           "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats", "lagp_predict_theta",
+           "lagp_predict_alc2", "lagp_mle"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -153,10 +165,30 @@ def lagp_predict(design, XX, T: int, params: lagp_params, n_per, ncand_per, mean
                              _stream(stream)))
 
 
-def lagp_predict_designs(design, XX, T: int, sel, sel_stride: int, n_per, n: int, d: float, g: float, mean, s2,
-                         df, var, status, stream=None) -> None:
-    _check(_lib.lagp_predict_designs(design, _ptr(XX), T, _ptr(sel), sel_stride, _ptr(n_per), n, d, g, _ptr(mean),
-                                     _ptr(s2), _ptr(df), _ptr(var), _ptr(status), _stream(stream)))
+def lagp_predict_theta(design, XX, T: int, params: lagp_params, d_per, n_per, ncand_per, mean, s2, df, var, sel,
+                       sel_stride: int, status, stream=None) -> None:
+    _check(_lib.lagp_predict_theta(design, _ptr(XX), T, C.byref(params), _ptr(d_per), _ptr(n_per), _ptr(ncand_per),
+                                   _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel), sel_stride, _ptr(status),
+                                   _stream(stream)))
+
+
+def lagp_predict_alc2(design, XX, T: int, params: lagp_params, mle: lagp_mle_params, d_per, n_per, ncand_per, mean,
+                      s2, df, var, sel, sel_stride: int, status, d1, d2, stream=None) -> None:
+    _check(_lib.lagp_predict_alc2(design, _ptr(XX), T, C.byref(params), C.byref(mle), _ptr(d_per), _ptr(n_per),
+                                  _ptr(ncand_per), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel), sel_stride,
+                                  _ptr(status), _ptr(d1), _ptr(d2), _stream(stream)))
+
+
+def lagp_mle(design, T: int, sel, sel_stride: int, n_per, n: int, d0_per, d0: float, g: float,
+             mle: lagp_mle_params, d_hat, iters, status, stream=None) -> None:
+    _check(_lib.lagp_mle(design, T, _ptr(sel), sel_stride, _ptr(n_per), n, _ptr(d0_per), d0, g, C.byref(mle),
+                         _ptr(d_hat), _ptr(iters), _ptr(status), _stream(stream)))
+
+
+def lagp_predict_designs(design, XX, T: int, sel, sel_stride: int, n_per, n: int, d: float, d_per, g: float, mean,
+                         s2, df, var, status, stream=None) -> None:
+    _check(_lib.lagp_predict_designs(design, _ptr(XX), T, _ptr(sel), sel_stride, _ptr(n_per), n, d, _ptr(d_per), g,
+                                     _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(status), _stream(stream)))
 
 
 def lagp_workspace_bytes(design, T: int, nmax: int, ncand_max: int) -> int:
@@ -244,10 +276,12 @@ def lagp_timing_enable(design, enable: bool) -> None:
 
 
 def lagp_phase_times(design):
-    """(knn_ms, design_ms, design_launches) summed since the last call."""
-    a, b, n = C.c_double(), C.c_double(), C.c_int64()
-    _check(_lib.lagp_phase_times(design, C.byref(a), C.byref(b), C.byref(n)))
-    return a.value, b.value, n.value
+    """(ms, design_launches) summed since the last call: ms is a dict of the
+    phases' device milliseconds (knn, design, mle, predict)."""
+    ms = (C.c_double * 4)()
+    n = C.c_int64()
+    _check(_lib.lagp_phase_times(design, ms, C.byref(n)))
+    return dict(zip(PHASES, ms)), n.value
 
 
 # ------------------------------------------------------- tensor conveniences
@@ -259,6 +293,23 @@ class Prediction:
     var: "torch.Tensor"
     sel: "torch.Tensor"
     status: "torch.Tensor"
+    theta1: Optional["torch.Tensor"] = None   # two-stage scheme: local MLE from the first designs
+    theta2: Optional["torch.Tensor"] = None   # ... and from the second designs
+
+
+# Newton controls of the local lengthscale search (the paper leaves them open).
+MLE_MAXIT = 100
+MLE_TOL = 1e-10
+
+
+def _outputs(T: int, nmax: int, dev) -> Prediction:
+    import torch
+    return Prediction(mean=torch.empty(T, dtype=torch.float64, device=dev),
+                      s2=torch.empty(T, dtype=torch.float64, device=dev),
+                      df=torch.empty(T, dtype=torch.int32, device=dev),
+                      var=torch.empty(T, dtype=torch.float64, device=dev),
+                      sel=torch.empty((T, max(nmax, 1)), dtype=torch.int32, device=dev),
+                      status=torch.empty(T, dtype=torch.int8, device=dev))
 
 
 class Design:
@@ -290,40 +341,72 @@ class Design:
         lagp_knn(self._h, XX, XX.shape[0], M, idx, M, stream)
         return idx
 
-    def predict_designs(self, XX, sel, d: float, g: float, n_per=None, stream=None) -> Prediction:
-        """Prediction from given local designs (sel: T x n int32 design indices)."""
-        import torch
+    def predict_designs(self, XX, sel, d: float, g: float, n_per=None, d_per=None, stream=None) -> Prediction:
+        """Prediction from given local designs (sel: T x n int32 design indices);
+        d_per (device float64[T]) gives each location its own lengthscale."""
         XX = XX.contiguous()
         sel = sel.contiguous()
         T, n = sel.shape
-        dev = XX.device
-        out = Prediction(mean=torch.empty(T, dtype=torch.float64, device=dev),
-                         s2=torch.empty(T, dtype=torch.float64, device=dev),
-                         df=torch.empty(T, dtype=torch.int32, device=dev),
-                         var=torch.empty(T, dtype=torch.float64, device=dev), sel=sel,
-                         status=torch.empty(T, dtype=torch.int8, device=dev))
-        lagp_predict_designs(self._h, XX, T, sel, n, n_per, n, d, g, out.mean, out.s2, out.df, out.var, out.status,
-                             stream)
+        out = _outputs(T, 0, XX.device)
+        out.sel = sel
+        lagp_predict_designs(self._h, XX, T, sel, n, n_per, n, d, d_per, g, out.mean, out.s2, out.df, out.var,
+                             out.status, stream)
+        return out
+
+    def mle(self, sel, d0, g: float, tmin: float, tmax: float, n_per=None, maxit: int = MLE_MAXIT,
+            tol: float = MLE_TOL, stream=None):
+        """Local MLE lengthscale of each design (sel: T x n int32); d0 a float or a
+        device float64[T] of starting values.  Returns (theta, iters, status)."""
+        import torch
+        sel = sel.contiguous()
+        T, n = sel.shape
+        dev = sel.device
+        theta = torch.empty(T, dtype=torch.float64, device=dev)
+        iters = torch.empty(T, dtype=torch.int32, device=dev)
+        status = torch.empty(T, dtype=torch.int8, device=dev)
+        per = d0 if torch.is_tensor(d0) else None
+        lagp_mle(self._h, T, sel, n, n_per, n, per, 1.0 if per is not None else float(d0), g,
+                 lagp_mle_params(tmin, tmax, maxit, tol), theta, iters, status, stream)
+        return theta, iters, status
+
+    def predict_alc2(self, XX, n0: int, n: int, ncand: int, d: float, g: float, tmin: float, tmax: float,
+                     maxit: int = MLE_MAXIT, tol: float = MLE_TOL, d_per=None, n_per=None, ncand_per=None,
+                     precision: int = LAGP_PREC_FP64, strict: bool = False, out: Optional[Prediction] = None,
+                     stream=None) -> Prediction:
+        """The two-stage scheme (designs, local MLE, designs again, MLE, prediction)."""
+        import torch
+        XX = XX.contiguous()
+        T = XX.shape[0]
+        nmax = int(n_per.max().item()) if (n_per is not None and T) else n
+        if out is None:
+            out = _outputs(T, nmax, XX.device)
+        if out.theta1 is None:
+            out.theta1 = torch.empty(T, dtype=torch.float64, device=XX.device)
+        if out.theta2 is None:
+            out.theta2 = torch.empty(T, dtype=torch.float64, device=XX.device)
+        prm = lagp_params(n0, n, ncand, d, g, precision, LAGP_STRICT if strict else 0)
+        lagp_predict_alc2(self._h, XX, T, prm, lagp_mle_params(tmin, tmax, maxit, tol), d_per, n_per, ncand_per,
+                          out.mean, out.s2, out.df, out.var, out.sel, out.sel.shape[1], out.status, out.theta1,
+                          out.theta2, stream)
         return out
 
     def predict(self, XX, n0: int, n: int, ncand: int, d: float, g: float, n_per=None, ncand_per=None,
                 precision: int = LAGP_PREC_FP64, strict: bool = False, out: Optional[Prediction] = None,
-                stream=None) -> Prediction:
-        import torch
+                d_per=None, stream=None) -> Prediction:
+        """Greedy ALC designs and prediction; d_per (device float64[T]) gives each
+        location its own lengthscale."""
         XX = XX.contiguous()
         T = XX.shape[0]
-        dev = XX.device
         nmax = int(n_per.max().item()) if (n_per is not None and T) else n
         if out is None:
-            out = Prediction(mean=torch.empty(T, dtype=torch.float64, device=dev),
-                             s2=torch.empty(T, dtype=torch.float64, device=dev),
-                             df=torch.empty(T, dtype=torch.int32, device=dev),
-                             var=torch.empty(T, dtype=torch.float64, device=dev),
-                             sel=torch.empty((T, max(nmax, 1)), dtype=torch.int32, device=dev),
-                             status=torch.empty(T, dtype=torch.int8, device=dev))
+            out = _outputs(T, nmax, XX.device)
         prm = lagp_params(n0, n, ncand, d, g, precision, LAGP_STRICT if strict else 0)
-        lagp_predict(self._h, XX, T, prm, n_per, ncand_per, out.mean, out.s2, out.df, out.var, out.sel,
-                     out.sel.shape[1], out.status, stream)
+        if d_per is None:
+            lagp_predict(self._h, XX, T, prm, n_per, ncand_per, out.mean, out.s2, out.df, out.var, out.sel,
+                         out.sel.shape[1], out.status, stream)
+        else:
+            lagp_predict_theta(self._h, XX, T, prm, d_per, n_per, ncand_per, out.mean, out.s2, out.df, out.var,
+                               out.sel, out.sel.shape[1], out.status, stream)
         return out
 
 

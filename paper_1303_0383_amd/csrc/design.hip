@@ -123,6 +123,7 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
     a.n = L.n;
     a.M = L.M;
     a.theta = L.theta;
+    a.theta_per = L.theta_per;
     a.eta = L.eta;
     a.mean = L.mean;
     a.s2 = L.s2;

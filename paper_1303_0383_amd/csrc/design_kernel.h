@@ -55,6 +55,7 @@ struct DesignArgs {
     const int32_t* M_per;
     int n0, n, M;
     double theta, eta;
+    const double* theta_per;  // nullable: per-location lengthscale (replaces theta)
     double* mean;
     double* s2;
     int32_t* df;
@@ -71,6 +72,15 @@ struct DesignArgs {
     const int32_t* order;    // nullable: work item -> location (else identity)
     const uint32_t* count;   // nullable: number of work items, read on the device (else T)
 };
+
+// A block-uniform double held in scalar registers.
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // ---- exact division helpers
 // a / b correctly rounded from y = RN(1/b): q = RN(a*y), r = a - q*b (exact
@@ -278,9 +288,8 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     const int p = P > 0 ? P : A.p;
     const int nmax = (A.nmax + 3) & ~3;   // padded: 4-row blocks read up to 3 entries ahead
     const int Mpad = CPT * DT;
-    const double theta = A.theta, eta = A.eta;
+    const double eta = A.eta;
     const double one_eta = 1.0 + eta;
-    const double rtheta = 1.0 / theta;
 
     // ---- LDS carve-up (doubles first, then ints)
     TW* ws = (TW*)smem;              // [nmax] column of the chosen candidate
@@ -320,6 +329,11 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         const int64_t t = A.order ? A.order[w] : w;
         const int n = A.n_per ? A.n_per[t] : A.n;
         const int M = A.M_per ? A.M_per[t] : A.M;
+        // A per-location lengthscale that is not a positive finite number
+        // fails the location (no greedy step is taken).
+        const double theta = A.theta_per ? uniform_f64(A.theta_per[t]) : A.theta;
+        const double rtheta = 1.0 / theta;
+        const bool theta_ok = theta > 0.0 && theta < INFINITY;
         // Slot columns k with k * DT >= M hold no candidate for any thread
         // (block-uniform).  When there are such columns, their global tile
         // rows are not written, their global reads are redirected to the last
@@ -414,8 +428,8 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 
         // ---- greedy steps
         int s_next = -1;
-        int notpd = 0;
-        for (int i = 0; i < n; ++i) {
+        int notpd = theta_ok ? 0 : 1;
+        for (int i = 0; i < n && !notpd; ++i) {
             const int s = (i < n0) ? forced[i] : s_next;
             if (s < 0 || s >= M) { notpd = 1; break; }
             const int s_lane = s % DT;

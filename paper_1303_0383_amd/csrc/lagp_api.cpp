@@ -315,6 +315,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
     P->uneven = hn || hm;
     P->mix = prm->precision == LAGP_PREC_SCORE_FP32;
     int32_t nmax = prm->n, Mmax = prm->ncand;
+    P->nmin = hn ? INT32_MAX : prm->n;
     if (P->uneven) {
         nmax = 0;
         Mmax = 0;
@@ -324,6 +325,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
             if (nt < prm->n0 || mt < nt || mt > N)
                 return fail(LAGP_E_INVAL, "location " + std::to_string(t) + ": need n0 <= n <= ncand <= N");
             nmax = std::max(nmax, nt);
+            P->nmin = std::min(P->nmin, nt);
             Mmax = std::max(Mmax, mt);
         }
     }
@@ -433,7 +435,41 @@ int prepare_plan(const lagp_design* d, const Plan& P)
             if (lagp::design_prepare(b.plan, &err)) return fail(LAGP_E_HIP, err);
         if (P.mix && lagp::design_prepare(c.redo, &err)) return fail(LAGP_E_HIP, err);
     }
-    if (P.mix && lagp::predict_prepare(P.nmax, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    if ((P.mix || P.alc2) && lagp::predict_prepare(P.nmax, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    if (P.alc2 && lagp::mle_prepare(P.nmax, d->dev.p, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    return LAGP_OK;
+}
+
+int check_mle_params(const lagp_mle_params* m)
+{
+    if (!m) return fail(LAGP_E_INVAL, "MLE parameters are NULL");
+    if (!(m->tmin > 0.0) || !(m->tmax > m->tmin) || !isfinite(m->tmax))
+        return fail(LAGP_E_INVAL, "need 0 < tmin < tmax, finite");
+    if (m->maxit < 1) return fail(LAGP_E_INVAL, "maxit must be >= 1");
+    if (!(m->tol > 0.0) || !isfinite(m->tol)) return fail(LAGP_E_INVAL, "tol must be positive and finite");
+    return LAGP_OK;
+}
+
+int plan_alc2(const lagp_design* d, const lagp_mle_params* mle, bool have_sel, Plan* P)
+{
+    int rc = check_mle_params(mle);
+    if (rc) return rc;
+    if (P->nmin < 2) return fail(LAGP_E_INVAL, "the two-stage scheme needs n >= 2 at every location");
+    if (lagp::mle_lds_bytes(P->nmax, d->dev.p, 256) > d->max_lds)
+        return fail(LAGP_E_INVAL, "n too large for the likelihood kernel");
+    if (lagp::predict_lds_bytes(P->nmax) > d->max_lds) return fail(LAGP_E_INVAL, "n too large for the prediction kernel");
+    P->alc2 = true;
+    P->mle = *mle;
+    const int64_t tc_max = std::min(kChunk, std::max<int64_t>(P->T, 1));
+    if (!have_sel && !P->own_sel) {
+        P->own_sel = true;
+        P->total -= P->sel_b;
+        P->sel_b = lagp::align256((size_t)tc_max * P->nmax * sizeof(int32_t));
+        P->total += P->sel_b;
+    }
+    P->sel1_b = lagp::align256((size_t)tc_max * P->nmax * sizeof(int32_t));
+    P->stage_b = 4 * lagp::align256((size_t)tc_max * sizeof(double)) + lagp::align256((size_t)tc_max);
+    P->total += P->sel1_b + P->stage_b;
     return LAGP_OK;
 }
 
@@ -444,11 +480,49 @@ __global__ void collect_failed_kernel(const int8_t* __restrict__ status, int64_t
     if (t < T && status[t] != LAGP_LOC_OK) list[atomicAdd(count, 1u)] = (int32_t)t;
 }
 
+// One design pass over chunk c into L's outputs: every bucket's launch, and
+// in the mixed mode the FP64 prediction and the FP64 redo of failed locations.
+static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::DesignLaunch L,
+                           const int32_t* order_dev, void* des_ws, int32_t* redo_list, uint32_t* redo_count,
+                           hipStream_t s)
+{
+    std::string err;
+    for (const Bucket& b : c.buckets) {
+        L.precision = P.prm.precision;
+        L.T = b.count;
+        L.n = b.nmax;
+        L.M = b.Mmax;
+        L.order = order_dev ? order_dev + c.t0 + b.first : nullptr;
+        int r = lagp::design_run(d->dev, L, b.plan, des_ws, P.design_b, s, &err);
+        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    }
+    if (P.mix) {
+        int r = lagp::predict_run(d->dev, L.XX, c.T, L.sel, L.sel_stride, L.n_per, c.nmax, L.theta, L.theta_per, L.eta,
+                                  L.mean, L.s2, L.df, L.var, L.status, d->max_lds, s, &err);
+        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        // FP32 ranking can lose positive definiteness where FP64 keeps it
+        // (tiny nuggets, near-duplicate neighbours): the locations that
+        // failed are redone in FP64 from a device-side list.
+        lagp::fill_u32(redo_count, 1, 0u, s);
+        hipLaunchKernelGGL(collect_failed_kernel, dim3((unsigned)((c.T + 255) / 256)), dim3(256), 0, s, L.status,
+                           c.T, redo_list, redo_count);
+        L.precision = LAGP_PREC_FP64;
+        L.T = c.T;
+        L.n = c.nmax;
+        L.M = c.Mmax;
+        L.order = redo_list;
+        L.count = redo_count;
+        r = lagp::design_run(d->dev, L, c.redo, des_ws, P.design_b, s, &err);
+        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    }
+    return LAGP_OK;
+}
+
 // Enqueues the whole plan on stream s.  ws holds P.total bytes; order_dev is
 // the uploaded work list (uneven plans); n_per / ncand_per are device arrays.
 int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_dev, const int32_t* n_per,
                  const int32_t* ncand_per, const double* XX, const Outputs& o, hipStream_t s, bool graph_safe,
-                 bool timing)
+                 bool timing, const ThetaIO* th)
 {
     char* q = ws;
     void* knn_ws = q;                  q += P.knn_b;
@@ -459,24 +533,39 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
     int8_t* st_ws = (int8_t*)q;        q += P.status_b;
     int32_t* redo_list = (int32_t*)q;
     uint32_t* redo_count = (uint32_t*)(q + (P.redo_b ? P.redo_b - 256 : 0));
+    q += P.redo_b;
+    int32_t* sel1_ws = (int32_t*)q;    q += P.sel1_b;
+    const int64_t tc_max = std::min(kChunk, std::max<int64_t>(P.T, 1));
+    const size_t vb = lagp::align256((size_t)tc_max * sizeof(double));
+    double* st_mean = (double*)q;
+    double* st_s2 = (double*)(q + vb);
+    double* th1_ws = (double*)(q + 2 * vb);
+    double* th2_ws = (double*)(q + 3 * vb);
+    int8_t* st_status = (int8_t*)(q + 4 * vb);
     const int p = d->dev.p;
+    const double* d_per = th ? th->d_per : nullptr;
+    // With `timing`, an event closes each phase interval on the stream.
+    auto mark = [&](int phase, int64_t launches) -> int {
+        if (!timing) return LAGP_OK;
+        hipEvent_t e = nullptr;
+        hipError_t h = hipEventCreate(&e);
+        if (h != hipSuccess) return hip_fail("hipEventCreate", h);
+        d->ev.push_back(e);
+        d->ev_phase.push_back(phase);
+        d->ev_launches.push_back(launches);
+        h = hipEventRecord(e, s);
+        return h == hipSuccess ? LAGP_OK : hip_fail("hipEventRecord", h);
+    };
     for (const Chunk& c : P.chunks) {
         std::string err;
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        if (timing) {
-            for (int k = 0; k < 3; ++k) {
-                hipError_t e = hipEventCreate(&ev[k]);
-                if (e != hipSuccess) return hip_fail("hipEventCreate", e);
-                d->ev.push_back(ev[k]);
-            }
-            d->ev_launches.push_back((int64_t)c.buckets.size());
-            (void)hipEventRecord(ev[0], s);
-        }
+        const int64_t launches = (int64_t)c.buckets.size();
+        int r = mark(-1, 0);
+        if (r) return r;
         const double* xx = XX + c.t0 * p;
-        int r = lagp::knn_run(d->dev, xx, c.T, P.Mmax, ncand_per ? ncand_per + c.t0 : nullptr, cand, P.Mmax, false,
-                              knn_ws, P.knn_b, s, d->num_cu, d->max_lds, &err, graph_safe);
+        r = lagp::knn_run(d->dev, xx, c.T, P.Mmax, ncand_per ? ncand_per + c.t0 : nullptr, cand, P.Mmax, false,
+                          knn_ws, P.knn_b, s, d->num_cu, d->max_lds, &err, graph_safe);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-        if (timing) (void)hipEventRecord(ev[1], s);
+        if ((r = mark(LAGP_PHASE_KNN, 0))) return r;
         lagp::DesignLaunch L;
         L.XX = xx;
         L.cand = cand;
@@ -485,6 +574,7 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
         L.M_per = ncand_per ? ncand_per + c.t0 : nullptr;
         L.n0 = P.prm.n0;
         L.theta = P.prm.d;
+        L.theta_per = d_per ? d_per + c.t0 : nullptr;
         L.eta = P.prm.g;
         L.mean = o.mean + c.t0;
         L.s2 = o.s2 + c.t0;
@@ -493,36 +583,67 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
         L.sel = o.sel ? o.sel + c.t0 * o.sel_stride : sel_ws;
         L.sel_stride = o.sel ? o.sel_stride : P.nmax;
         L.status = o.status ? o.status + c.t0 : (P.own_status ? st_ws + c.t0 : nullptr);
-        for (const Bucket& b : c.buckets) {
-            L.precision = P.prm.precision;
-            L.T = b.count;
-            L.n = b.nmax;
-            L.M = b.Mmax;
-            L.order = order_dev ? order_dev + c.t0 + b.first : nullptr;
-            r = lagp::design_run(d->dev, L, b.plan, des_ws, P.design_b, s, &err);
+        if (!P.alc2) {
+            r = enqueue_designs(d, P, c, L, order_dev, des_ws, redo_list, redo_count, s);
+            if (r) return r;
+            if ((r = mark(LAGP_PHASE_DESIGN, launches))) return r;
+        } else {
+            // Section 4.2, one repetition: designs at theta0, the local MLE
+            // theta1, designs at theta1, the local MLE theta2 (started from
+            // theta1), and the prediction from the second designs at theta2.
+            double* th1 = (th && th->d1) ? th->d1 + c.t0 : th1_ws;
+            double* th2 = (th && th->d2) ? th->d2 + c.t0 : th2_ws;
+            lagp::DesignLaunch S = L;
+            S.mean = st_mean;
+            S.s2 = st_s2;
+            S.df = nullptr;
+            S.var = nullptr;
+            S.status = st_status;
+            S.sel = sel1_ws;
+            S.sel_stride = P.nmax;
+            r = enqueue_designs(d, P, c, S, order_dev, des_ws, redo_list, redo_count, s);
+            if (r) return r;
+            if ((r = mark(LAGP_PHASE_DESIGN, launches))) return r;
+            lagp::MleArgs m;
+            m.Xaos = d->dev.Xaos;
+            m.y = d->dev.y;
+            m.p = p;
+            m.N = d->dev.N;
+            m.T = c.T;
+            m.sel = sel1_ws;
+            m.sel_stride = P.nmax;
+            m.n_per = L.n_per;
+            m.n = P.prm.n;
+            m.nmax = c.nmax;
+            m.theta0_per = L.theta_per;
+            m.theta0 = P.prm.d;
+            m.eta = P.prm.g;
+            m.tmin = P.mle.tmin;
+            m.tmax = P.mle.tmax;
+            m.maxit = P.mle.maxit;
+            m.tol = P.mle.tol;
+            m.theta_out = th1;
+            r = lagp::mle_run(m, d->max_lds, s, &err);
             if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-        }
-        if (P.mix) {
-            r = lagp::predict_run(d->dev, xx, c.T, L.sel, L.sel_stride, L.n_per, c.nmax, P.prm.d, P.prm.g, L.mean,
+            if ((r = mark(LAGP_PHASE_MLE, 0))) return r;
+            S.theta_per = th1;
+            S.sel = L.sel;
+            S.sel_stride = L.sel_stride;
+            r = enqueue_designs(d, P, c, S, order_dev, des_ws, redo_list, redo_count, s);
+            if (r) return r;
+            if ((r = mark(LAGP_PHASE_DESIGN, launches))) return r;
+            m.sel = L.sel;
+            m.sel_stride = L.sel_stride;
+            m.theta0_per = th1;
+            m.theta_out = th2;
+            r = lagp::mle_run(m, d->max_lds, s, &err);
+            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+            if ((r = mark(LAGP_PHASE_MLE, 0))) return r;
+            r = lagp::predict_run(d->dev, xx, c.T, L.sel, L.sel_stride, L.n_per, c.nmax, P.prm.d, th2, P.prm.g, L.mean,
                                   L.s2, L.df, L.var, L.status, d->max_lds, s, &err);
             if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-            // FP32 ranking can lose positive definiteness where FP64 keeps it
-            // (tiny nuggets, near-duplicate neighbours): the locations that
-            // failed are redone in FP64 from a device-side list.
-            lagp::fill_u32(redo_count, 1, 0u, s);
-            hipLaunchKernelGGL(collect_failed_kernel, dim3((unsigned)((c.T + 255) / 256)), dim3(256), 0, s, L.status,
-                               c.T, redo_list, redo_count);
-            L.precision = LAGP_PREC_FP64;
-            L.T = c.T;
-            L.n = c.nmax;
-            L.M = c.Mmax;
-            L.order = redo_list;
-            L.count = redo_count;
-            r = lagp::design_run(d->dev, L, c.redo, des_ws, P.design_b, s, &err);
-            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-            L.count = nullptr;
+            if ((r = mark(LAGP_PHASE_PREDICT, 0))) return r;
         }
-        if (timing) (void)hipEventRecord(ev[2], s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail("launch", e);
@@ -570,12 +691,20 @@ int lagp_workspace_bytes(const lagp_design* design, int64_t T, int32_t nmax, int
     return LAGP_OK;
 }
 
-int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
-                 const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
-                 int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+}  // extern "C"
+
+// lagp_predict, lagp_predict_theta and lagp_predict_alc2 (mle non-null).
+static int run_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                       const ThetaIO& th, const lagp_mle_params* mle, const int32_t* n_per, const int32_t* ncand_per,
+                       double* mean, double* s2, int32_t* df, double* var, int32_t* sel, int64_t sel_stride,
+                       int8_t* status, void* stream)
 {
     if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
     if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
+    if (mle) {
+        int rc = check_mle_params(mle);
+        if (rc) return rc;
+    }
     if (T == 0) {
         Plan P;
         return build_plan(design, prm, 0, nullptr, nullptr, true, true, &P);
@@ -583,7 +712,7 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     if (!XX || !mean || !s2) return fail(LAGP_E_INVAL, "XX, mean and s2 are required");
     int rc = check_device(design);
     if (rc) return rc;
-    const void* devptrs[] = {XX, n_per, ncand_per};
+    const void* devptrs[] = {XX, n_per, ncand_per, th.d_per, th.d1, th.d2};
     for (const void* q : devptrs)
         if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
     const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
@@ -605,6 +734,10 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
     if (rc) return rc;
     rc = check_outputs(o, P.nmax);
     if (rc) return rc;
+    if (mle) {
+        rc = plan_alc2(design, mle, sel != nullptr, &P);
+        if (rc) return rc;
+    }
     lagp_design* d = const_cast<lagp_design*>(design);
     rc = ensure_ws(d, P.total, s);
     if (rc) return rc;
@@ -617,7 +750,7 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         if (e == hipSuccess) e = hipStreamSynchronize(s);   // P.order is released on return
         if (e != hipSuccess) return hip_fail("work list copy", e);
     }
-    rc = enqueue_plan(d, P, (char*)d->ws, order_dev, n_per, ncand_per, XX, o, s, false, d->timing);
+    rc = enqueue_plan(d, P, (char*)d->ws, order_dev, n_per, ncand_per, XX, o, s, false, d->timing, &th);
     if (rc) return rc;
     if (prm->flags & LAGP_STRICT) {
         if (!status) return fail(LAGP_E_INVAL, "strict mode needs the status output");
@@ -628,6 +761,103 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
         for (int8_t v : hs)
             if (v != LAGP_LOC_OK) return fail(LAGP_E_NOTPD, "some location's local covariance was not positive definite");
     }
+    return LAGP_OK;
+}
+
+extern "C" {
+
+int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                 const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var,
+                 int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+{
+    return run_predict(design, XX, T, prm, ThetaIO{}, nullptr, n_per, ncand_per, mean, s2, df, var, sel, sel_stride,
+                       status, stream);
+}
+
+int lagp_predict_theta(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                       const double* d_per, const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2,
+                       int32_t* df, double* var, int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+{
+    if (!d_per && T > 0) return fail(LAGP_E_INVAL, "d_per is required");
+    ThetaIO th;
+    th.d_per = d_per;
+    return run_predict(design, XX, T, prm, th, nullptr, n_per, ncand_per, mean, s2, df, var, sel, sel_stride, status,
+                       stream);
+}
+
+int lagp_predict_alc2(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                      const lagp_mle_params* mle, const double* d_per, const int32_t* n_per,
+                      const int32_t* ncand_per, double* mean, double* s2, int32_t* df, double* var, int32_t* sel,
+                      int64_t sel_stride, int8_t* status, double* d1, double* d2, void* stream)
+{
+    if (!mle) return fail(LAGP_E_INVAL, "MLE parameters are NULL");
+    ThetaIO th;
+    th.d_per = d_per;
+    th.d1 = d1;
+    th.d2 = d2;
+    return run_predict(design, XX, T, prm, th, mle, n_per, ncand_per, mean, s2, df, var, sel, sel_stride, status,
+                       stream);
+}
+
+int lagp_mle(const lagp_design* design, int64_t T, const int32_t* sel, int64_t sel_stride, const int32_t* n_per,
+             int32_t n, const double* d0_per, double d0, double g, const lagp_mle_params* mle, double* d_hat,
+             int32_t* iters, int8_t* status, void* stream)
+{
+    if (!design) return fail(LAGP_E_INVAL, "design is NULL");
+    if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
+    int rc = check_mle_params(mle);
+    if (rc) return rc;
+    if (!d0_per && (!(d0 > 0.0) || !isfinite(d0))) return fail(LAGP_E_INVAL, "lengthscale d0 must be positive and finite");
+    if (!(g >= 0.0) || !isfinite(g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
+    if (T == 0) return LAGP_OK;
+    if (!sel || !d_hat) return fail(LAGP_E_INVAL, "sel and d_hat are required");
+    const void* devptrs[] = {sel, n_per, d0_per, d_hat, iters, status};
+    for (const void* q : devptrs)
+        if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
+    rc = check_device(design);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t nmax = n;
+    if (n_per) {
+        std::vector<int32_t> hn(T);
+        hipError_t e = hipMemcpyAsync(hn.data(), n_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail("per-location size copy", e);
+        nmax = 0;
+        for (int64_t t = 0; t < T; ++t) {
+            if (hn[t] < 2) return fail(LAGP_E_INVAL, "every n must be >= 2");
+            nmax = std::max(nmax, hn[t]);
+        }
+    }
+    if (nmax < 2) return fail(LAGP_E_INVAL, "n must be >= 2");
+    if (sel_stride < nmax) return fail(LAGP_E_INVAL, "sel_stride must be >= n");
+    if (T > INT32_MAX) return fail(LAGP_E_INVAL, "T above 2^31 - 1");
+    std::string err;
+    int r = lagp::mle_prepare(nmax, design->dev.p, design->max_lds, &err);
+    if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    lagp::MleArgs m;
+    m.Xaos = design->dev.Xaos;
+    m.y = design->dev.y;
+    m.p = design->dev.p;
+    m.N = design->dev.N;
+    m.T = T;
+    m.sel = sel;
+    m.sel_stride = sel_stride;
+    m.n_per = n_per;
+    m.n = n;
+    m.nmax = nmax;
+    m.theta0_per = d0_per;
+    m.theta0 = d0;
+    m.eta = g;
+    m.tmin = mle->tmin;
+    m.tmax = mle->tmax;
+    m.maxit = mle->maxit;
+    m.tol = mle->tol;
+    m.theta_out = d_hat;
+    m.iters = iters;
+    m.status = status;
+    r = lagp::mle_run(m, design->max_lds, s, &err);
+    if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     return LAGP_OK;
 }
 
@@ -761,16 +991,17 @@ int lagp_design_set_variant(lagp_design* d, int32_t threads, int32_t coords)
 }
 
 int lagp_predict_designs(const lagp_design* design, const double* XX, int64_t T, const int32_t* sel,
-                         int64_t sel_stride, const int32_t* n_per, int32_t n, double dlen, double g, double* mean,
-                         double* s2, int32_t* df, double* var, int8_t* status, void* stream)
+                         int64_t sel_stride, const int32_t* n_per, int32_t n, double dlen, const double* d_per,
+                         double g, double* mean, double* s2, int32_t* df, double* var, int8_t* status, void* stream)
 {
     if (!design) return fail(LAGP_E_INVAL, "design is NULL");
     if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
-    if (!(dlen > 0.0) || !isfinite(dlen)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
+    if (!d_per && (!(dlen > 0.0) || !isfinite(dlen)))
+        return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
     if (!(g >= 0.0) || !isfinite(g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
     if (T == 0) return LAGP_OK;
     if (!XX || !sel || !mean || !s2) return fail(LAGP_E_INVAL, "XX, sel, mean and s2 are required");
-    const void* devptrs[] = {XX, sel, mean, s2, df, var, status, n_per};
+    const void* devptrs[] = {XX, sel, mean, s2, df, var, status, n_per, d_per};
     for (const void* q : devptrs)
         if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
     int rc = check_device(design);
@@ -793,7 +1024,7 @@ int lagp_predict_designs(const lagp_design* design, const double* XX, int64_t T,
     std::string err;
     int r = lagp::predict_prepare(nmax, design->max_lds, &err);
     if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-    r = lagp::predict_run(design->dev, XX, T, sel, sel_stride, n_per, nmax, dlen, g, mean, s2, df, var, status,
+    r = lagp::predict_run(design->dev, XX, T, sel, sel_stride, n_per, nmax, dlen, d_per, g, mean, s2, df, var, status,
                           design->max_lds, s, &err);
     if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     return LAGP_OK;
@@ -806,28 +1037,35 @@ int lagp_timing_enable(lagp_design* d, int enable)
     return LAGP_OK;
 }
 
-int lagp_phase_times(lagp_design* d, double* knn_ms, double* design_ms, int64_t* launches)
+int lagp_phase_times(lagp_design* d, double* ms, int64_t* design_launches)
 {
     if (!d) return fail(LAGP_E_INVAL, "design is NULL");
-    double a = 0.0, b = 0.0;
+    double sum[LAGP_PHASES] = {};
     int64_t n = 0;
-    for (size_t k = 0; k + 2 < d->ev.size(); k += 3) {
-        hipError_t e = hipEventSynchronize(d->ev[k + 2]);
-        if (e != hipSuccess) return hip_fail("hipEventSynchronize", e);
-        float x = 0.f, y = 0.f;
-        if (hipEventElapsedTime(&x, d->ev[k], d->ev[k + 1]) != hipSuccess ||
-            hipEventElapsedTime(&y, d->ev[k + 1], d->ev[k + 2]) != hipSuccess)
-            return fail(LAGP_E_HIP, "hipEventElapsedTime failed");
-        a += x;
-        b += y;
-        n += d->ev_launches[k / 3];
+    int rc = LAGP_OK;
+    if (!d->ev.empty()) {
+        hipError_t e = hipEventSynchronize(d->ev.back());
+        if (e != hipSuccess) rc = hip_fail("hipEventSynchronize", e);
+    }
+    for (size_t k = 1; rc == LAGP_OK && k < d->ev.size(); ++k) {
+        const int ph = d->ev_phase[k];
+        if (ph < 0) continue;
+        float x = 0.f;
+        if (hipEventElapsedTime(&x, d->ev[k - 1], d->ev[k]) != hipSuccess) {
+            rc = fail(LAGP_E_HIP, "hipEventElapsedTime failed");
+            break;
+        }
+        sum[ph] += x;
+        n += d->ev_launches[k];
     }
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
     d->ev.clear();
+    d->ev_phase.clear();
     d->ev_launches.clear();
-    if (knn_ms) *knn_ms = a;
-    if (design_ms) *design_ms = b;
-    if (launches) *launches = n;
+    if (rc) return rc;
+    if (ms)
+        for (int k = 0; k < LAGP_PHASES; ++k) ms[k] = sum[k];
+    if (design_launches) *design_launches = n;
     return LAGP_OK;
 }
 

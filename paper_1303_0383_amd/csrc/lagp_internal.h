@@ -77,6 +77,7 @@ struct DesignLaunch {
     const int32_t* M_per = nullptr;
     int32_t n0 = 0, n = 0, M = 0;  // uniform values (maxima when per-location arrays are given)
     double theta = 1.0, eta = 0.0;
+    const double* theta_per = nullptr;  // nullable: per-location lengthscale (replaces theta)
     int32_t precision = 0;
     const int32_t* order = nullptr;   // work item -> location (nullable: identity over T)
     const uint32_t* count = nullptr;  // device-side item count (nullable: T items)
@@ -125,8 +126,36 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
 // ---- prediction from given local designs (predict.hip)
 size_t predict_lds_bytes(int nmax);
 int predict_prepare(int32_t nmax, size_t max_lds, std::string* err);
+// theta_per (nullable) gives each location its own lengthscale.
 int predict_run(const DeviceDesign& D, const double* XX, int64_t T, const int32_t* sel, int64_t sel_stride,
-                const int32_t* n_per, int32_t nmax, double theta, double eta, double* mean, double* s2,
-                int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream, std::string* err);
+                const int32_t* n_per, int32_t nmax, double theta, const double* theta_per, double eta, double* mean,
+                double* s2, int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream,
+                std::string* err);
+
+// ---- local maximum-likelihood lengthscale of given designs (mle.hip)
+struct MleArgs {
+    const double* Xaos = nullptr;   // design, N x p row-major
+    const double* y = nullptr;
+    int p = 0;
+    int64_t N = 0;
+    int64_t T = 0;
+    const int32_t* sel = nullptr;   // T x sel_stride local design indices
+    int64_t sel_stride = 0;
+    const int32_t* n_per = nullptr; // nullable: per-location design size
+    int n = 0;                      // uniform design size
+    int nmax = 0;                   // largest design size (sizes LDS)
+    const double* theta0_per = nullptr;   // nullable: per-location starting lengthscale
+    double theta0 = 1.0;
+    double eta = 0.0;
+    double tmin = 0.0, tmax = 0.0;  // search interval
+    int maxit = 0;
+    double tol = 0.0;
+    double* theta_out = nullptr;    // T: the estimate (NaN where the design failed)
+    int32_t* iters = nullptr;       // nullable: Newton iterates taken
+    int8_t* status = nullptr;       // nullable: 0 OK, 1 failed
+};
+size_t mle_lds_bytes(int nmax, int p, int threads);
+int mle_prepare(int32_t nmax, int p, size_t max_lds, std::string* err);
+int mle_run(const MleArgs& a, size_t max_lds, hipStream_t stream, std::string* err);
 
 }  // namespace lagp

@@ -24,8 +24,12 @@ struct lagp_design {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool timing = false;
-    std::vector<hipEvent_t> ev;   // triples: before kNN, after kNN, after design
-    std::vector<int64_t> ev_launches;   // design-kernel launches per triple
+    // Phase timing: events on the launch stream; ev_phase[k] names the phase
+    // of the interval that ends at ev[k] (LAGP_PHASE_*; -1 starts a chunk),
+    // ev_launches[k] the design-kernel launches in it.
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_phase;
+    std::vector<int64_t> ev_launches;
     std::string arch;                   // e.g. "gfx950"
     int force_threads = 0;              // kernel-variant override (0: table or model)
     int force_coords = -1;
@@ -57,11 +61,23 @@ struct Plan {
     lagp_params prm{};
     int64_t T = 0;
     int32_t nmax = 0, Mmax = 0;
+    int32_t nmin = 0;             // smallest design size
     bool uneven = false, mix = false, own_sel = false, own_status = false;
+    bool alc2 = false;            // two-stage scheme with local lengthscale inference
+    lagp_mle_params mle{};
     std::vector<Chunk> chunks;
     std::vector<int32_t> order;   // chunk-relative locations, chunk c at [t0, t0 + T)
     // workspace layout
-    size_t knn_b = 0, cand_b = 0, design_b = 0, order_b = 0, sel_b = 0, status_b = 0, redo_b = 0, total = 0;
+    size_t knn_b = 0, cand_b = 0, design_b = 0, order_b = 0, sel_b = 0, status_b = 0, redo_b = 0;
+    size_t sel1_b = 0, stage_b = 0;   // two-stage: first designs; stage outputs and lengthscales
+    size_t total = 0;
+};
+
+// Lengthscale inputs and outputs of the entry points that take them.
+struct ThetaIO {
+    const double* d_per = nullptr;  // device T: per-location lengthscale (first design pass)
+    double* d1 = nullptr;           // two-stage outputs, device T (nullable)
+    double* d2 = nullptr;
 };
 
 struct Outputs {
@@ -78,6 +94,9 @@ struct Outputs {
 // the plan for T locations.
 int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
                bool have_sel, bool have_status, Plan* P);
+// Turns a plan into the two-stage scheme: checks the search controls and
+// n >= 2, and adds the stage workspace.  have_sel: the caller passes sel.
+int plan_alc2(const lagp_design* d, const lagp_mle_params* mle, bool have_sel, Plan* P);
 // Host-side kernel set-up for every variant the plan launches (outside capture).
 int prepare_plan(const lagp_design* d, const Plan& P);
 // Enqueues the plan on stream s: kernel launches only.  ws holds P.total
@@ -86,7 +105,8 @@ int prepare_plan(const lagp_design* d, const Plan& P);
 // With `timing` the phases are bracketed by HIP events kept on the design.
 int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_dev, const int32_t* n_per,
                  const int32_t* ncand_per, const double* XX, const Outputs& o, hipStream_t s, bool graph_safe,
-                 bool timing);
+                 bool timing, const ThetaIO* th = nullptr);
+int check_mle_params(const lagp_mle_params* mle);
 int check_outputs(const Outputs& o, int32_t nmax);
 
 }  // namespace lagp_rt

@@ -1,0 +1,331 @@
+// mle.hip -- local maximum-likelihood lengthscale of given local designs.
+//
+// The concentrated log likelihood of a local design (eq gpk of Section 2;
+// constants dropped)
+//   l(theta) = -1/2 log|K| - n/2 log psi,   psi = Y'K^{-1}Y,
+// and its first two derivatives (eqs dl, d2l of SM Section 2)
+//   l'  = -1/2 tr(K^{-1} dK) + n/2 q / psi,                 q  = Y'K^{-1} dK K^{-1}Y,
+//   l'' = -1/2 [tr(K^{-1} d2K) - tr((K^{-1} dK)^2)]
+//         + n/2 (r - 2 sq) / psi + n/2 q^2 / psi^2,          r  = Y'K^{-1} d2K K^{-1}Y,
+//                                                            sq = Y'K^{-1} dK K^{-1} dK K^{-1}Y.
+// For the isotropic Gaussian kernel K(a,b) = exp(-d2/theta) the off-diagonal
+// entries of dK and d2K are K d2/theta^2 and dK (d2/theta^2 - 2/theta); the
+// diagonal (1 + g) does not depend on theta.  Section 3.2 finds the maximum
+// once per location, after the design is complete, by a Newton-like search
+// with these derivatives.
+//
+// One workgroup per location.  For each Newton iterate it
+//   * builds K (packed lower triangle) and dK (packed strictly-lower
+//     triangle) from the design coordinates held in LDS;
+//   * factorises K right-looking in place, carrying u = L^{-1} Y, and keeps
+//     the pivots L_kk;
+//   * overwrites L with L^{-1} in place by Gauss-Jordan elimination of one
+//     column per pair of barriers (the column about to be eliminated is
+//     copied aside first);
+//   * forms w = K^{-1} Y = L^{-T} u and k = dK w, and from them
+//     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
+//   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
+//     K^{-1} = L^{-T} L^{-1} computed as they are used, and
+//     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of PW columns of
+//     H = dK L^{-T} at a time;
+//   * takes the safeguarded Newton step on l'(theta) = 0.
+// The step rule: where l'' < 0 the step is -l'/l''; elsewhere it is theta in
+// the direction of l'; a step leaving (tmin, tmax) goes half way to the
+// bound instead; the search stops when a step moves theta by at most
+// tol * theta, or after maxit iterates.
+//
+// A design with an index outside [0, N), fewer than 2 points, or a
+// non-positive pivot at any iterate gives theta = NaN (and status NOTPD).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "lagp_internal.h"
+
+namespace lagp {
+
+namespace {
+
+constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product
+constexpr int NRED = 7; // sums reduced per iterate
+
+__device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }   // lower, diagonal included
+__device__ __forceinline__ int sl(int i, int k) { return i * (i - 1) / 2 + k; }    // strictly lower, i > k
+
+// Row of packed-lower index e (a(a+1)/2 <= e < (a+1)(a+2)/2).
+__device__ __forceinline__ int row_of(int e)
+{
+    int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while (a > 0 && a * (a + 1) / 2 > e) --a;
+    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    return a;
+}
+
+__device__ __forceinline__ double sqdist_rows(const double* xs, int a, int b, int p)
+{
+    double s = 0.0;
+    for (int c = 0; c < p; ++c) {
+        const double d = xs[a * p + c] - xs[b * p + c];
+        s += d * d;
+    }
+    return s;
+}
+
+template <int MT>
+__device__ __forceinline__ void block_sum(double (&v)[NRED], double* red, int tid)
+{
+#pragma unroll
+    for (int k = 0; k < NRED; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) red[k * (MT / 64) + (tid >> 6)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) {
+        double s = red[k * (MT / 64)];
+        for (int w = 1; w < MT / 64; ++w) s += red[k * (MT / 64) + w];
+        v[k] = s;
+    }
+}
+
+template <int MT>
+__global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
+{
+    extern __shared__ double sm[];
+    const int64_t t = blockIdx.x;
+    if (t >= A.T) return;
+    const int tid = threadIdx.x;
+    const int p = A.p;
+    const int n = A.n_per ? A.n_per[t] : A.n;
+    const int32_t* D = A.sel + t * A.sel_stride;
+    const int nm = A.nmax;
+    // LDS carve-up (doubles), sized for nmax
+    double* xs = sm;                              // [nmax][p] design coordinates
+    double* Tm = xs + (size_t)nm * p;             // packed lower: K -> L -> L^{-1}
+    double* Cd = Tm + (size_t)nm * (nm + 1) / 2;  // packed strictly lower: dK
+    double* H = Cd + (size_t)nm * (nm - 1) / 2;   // [nmax][PW] panel of dK L^{-T}
+    double* yv = H + (size_t)nm * PW;             // Y
+    double* u = yv + nm;                          // L^{-1} Y
+    double* w = u + nm;                           // K^{-1} Y
+    double* kw = w + nm;                          // dK K^{-1} Y
+    double* col = kw + nm;                        // column being eliminated
+    double* piv = col + nm;                       // pivots L_kk
+    double* red = piv + nm;                       // [NRED][MT/64]
+    __shared__ int bad, done;
+    __shared__ double sh_theta;
+
+    if (tid == 0) bad = (n < 2 || n > nm) ? 1 : 0;
+    __syncthreads();
+    if (!bad)
+        for (int a = tid; a < n; a += MT)
+            if (D[a] < 0 || D[a] >= A.N) bad = 1;
+    __syncthreads();
+
+    double theta = NAN;
+    int it = 0;
+    if (!bad) {
+        for (int e = tid; e < n * p; e += MT) xs[e] = A.Xaos[(int64_t)D[e / p] * p + e % p];
+        for (int a = tid; a < n; a += MT) yv[a] = A.y[D[a]];
+        const double th0 = A.theta0_per ? A.theta0_per[t] : A.theta0;
+        theta = (th0 > A.tmin && th0 < A.tmax) ? th0 : sqrt(A.tmin * A.tmax);
+        const int ntri = n * (n + 1) / 2;
+        while (it < A.maxit) {
+            __syncthreads();
+            const double th2 = theta * theta;
+            // ---- K and dK
+            for (int e = tid; e < ntri; e += MT) {
+                const int a = row_of(e), b = e - a * (a + 1) / 2;
+                if (a == b) {
+                    Tm[e] = 1.0 + A.eta;
+                } else {
+                    const double d2 = sqdist_rows(xs, a, b, p);
+                    const double k = exp(-(d2 / theta));
+                    Tm[e] = k;
+                    Cd[sl(a, b)] = k * d2 / th2;
+                }
+            }
+            for (int a = tid; a < n; a += MT) u[a] = yv[a];
+            __syncthreads();
+            // ---- Cholesky, right-looking, with u = L^{-1} Y
+            int fail = 0;
+            for (int m = 0; m < n; ++m) {
+                const double pm = Tm[tri(m, m)];
+                if (!(pm > 0.0)) { fail = 1; break; }   // uniform: every thread read the same pivot
+                const double dm = sqrt(pm);
+                __syncthreads();   // the pivot has been read everywhere before it is overwritten
+                if (tid == 0) {
+                    Tm[tri(m, m)] = dm;
+                    piv[m] = dm;
+                    u[m] = u[m] / dm;
+                }
+                for (int i = m + 1 + tid; i < n; i += MT) Tm[tri(i, m)] = Tm[tri(i, m)] / dm;
+                __syncthreads();
+                // trailing triangle rows i > m, columns m < k <= i; and u
+                const int tn = n - m - 1;
+                int ii = 0, kk = tid;
+                while (ii < tn && kk > ii) { kk -= ii + 1; ++ii; }
+                for (; ii < tn;) {
+                    const int i = m + 1 + ii, k = m + 1 + kk;
+                    Tm[tri(i, k)] -= Tm[tri(i, m)] * Tm[tri(k, m)];
+                    kk += MT;
+                    while (ii < tn && kk > ii) { kk -= ii + 1; ++ii; }
+                }
+                const double um = u[m];
+                for (int i = m + 1 + tid; i < n; i += MT) u[i] -= Tm[tri(i, m)] * um;
+                __syncthreads();
+            }
+            if (fail) {
+                if (tid == 0) bad = 1;
+                break;
+            }
+            // ---- L^{-1} in place: Gauss-Jordan on the columns of L
+            for (int k = 0; k < n; ++k) {
+                const double lk = piv[k];
+                for (int c = tid; c <= k; c += MT)
+                    Tm[tri(k, c)] = (c == k) ? 1.0 / lk : Tm[tri(k, c)] / lk;
+                for (int i = k + 1 + tid; i < n; i += MT) col[i] = Tm[tri(i, k)];
+                __syncthreads();
+                const int rows = n - k - 1, w1 = k + 1;
+                for (int e = tid; e < rows * w1; e += MT) {
+                    const int i = k + 1 + e / w1, c = e - (e / w1) * w1;
+                    if (c == k) Tm[tri(i, k)] = -(col[i] * Tm[tri(k, k)]);
+                    else Tm[tri(i, c)] -= col[i] * Tm[tri(k, c)];
+                }
+                __syncthreads();
+            }
+            // ---- w = L^{-T} u, then k = dK w
+            for (int b = tid; b < n; b += MT) {
+                double s = 0.0;
+                for (int a = b; a < n; ++a) s += Tm[tri(a, b)] * u[a];
+                w[b] = s;
+            }
+            __syncthreads();
+            for (int a = tid; a < n; a += MT) {
+                double s = 0.0;
+                for (int b = 0; b < a; ++b) s += Cd[sl(a, b)] * w[b];
+                for (int b = a + 1; b < n; ++b) s += Cd[sl(b, a)] * w[b];
+                kw[a] = s;
+            }
+            __syncthreads();
+            // sums: 0 psi, 1 q, 2 sq, 3 r, 4 t1, 5 t2, 6 t3
+            double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int a = tid; a < n; a += MT) {
+                acc[0] += u[a] * u[a];
+                acc[1] += w[a] * kw[a];
+                double z = 0.0;
+                for (int b = 0; b <= a; ++b) z += Tm[tri(a, b)] * kw[b];
+                acc[2] += z * z;
+            }
+            // off-diagonal pairs a > b: K^{-1}_ab = sum_{k >= a} Li_ka Li_kb
+            const double r2t = 2.0 / theta;
+            const int nsl = n * (n - 1) / 2;
+            for (int e = tid; e < nsl; e += MT) {
+                const int a = row_of(e) + 1, b = e - a * (a - 1) / 2;
+                double ki = 0.0;
+                for (int k = a; k < n; ++k) ki += Tm[tri(k, a)] * Tm[tri(k, b)];
+                const double kd = Cd[e];
+                const double d2 = sqdist_rows(xs, a, b, p);
+                const double kdd = kd * (d2 / th2 - r2t);
+                acc[3] += 2.0 * (w[a] * w[b]) * kdd;
+                acc[4] += 2.0 * ki * kd;
+                acc[5] += 2.0 * ki * kdd;
+            }
+            // ---- tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2, PW columns at a time
+            for (int j0 = 0; j0 < n; j0 += PW) {
+                const int pw = (n - j0) < PW ? (n - j0) : PW;
+                // H[a][jj] = sum_{b <= j} dK_ab Li_jb, j = j0 + jj
+                for (int e = tid; e < n * pw; e += MT) {
+                    const int a = e / pw, jj = e - a * pw, j = j0 + jj;
+                    double s = 0.0;
+                    for (int b = 0; b <= j; ++b) {
+                        const double kd = (a > b) ? Cd[sl(a, b)] : (a < b ? Cd[sl(b, a)] : 0.0);
+                        s += kd * Tm[tri(j, b)];
+                    }
+                    H[a * PW + jj] = s;
+                }
+                __syncthreads();
+                // M_ij = sum_{a <= i} Li_ia H_aj for i >= j
+                for (int e = tid; e < n * pw; e += MT) {
+                    const int i = e / pw, jj = e - i * pw, j = j0 + jj;
+                    if (i < j) continue;
+                    double s = 0.0;
+                    for (int a = 0; a <= i; ++a) s += Tm[tri(i, a)] * H[a * PW + jj];
+                    acc[6] += (i == j ? 1.0 : 2.0) * (s * s);
+                }
+                __syncthreads();
+            }
+            block_sum<MT>(acc, red, tid);
+            if (tid == 0) {
+                const double psi = acc[0], q = acc[1], sq = acc[2], r = acc[3], t1 = acc[4], t2 = acc[5], t3 = acc[6];
+                const double nn = (double)n;
+                const double l1 = -0.5 * t1 + 0.5 * nn * q / psi;
+                const double l2 = -0.5 * (t2 - t3) + 0.5 * nn * (r - 2.0 * sq) / psi + 0.5 * nn * q * q / (psi * psi);
+                const double step = (l2 < 0.0) ? -l1 / l2 : (l1 > 0.0 ? theta : -theta);
+                double next = theta + step;
+                if (!(next > A.tmin)) next = 0.5 * (theta + A.tmin);
+                if (!(next < A.tmax)) next = 0.5 * (theta + A.tmax);
+                done = fabs(next - theta) <= A.tol * theta;
+                sh_theta = next;
+            }
+            __syncthreads();
+            theta = sh_theta;
+            ++it;
+            if (done) break;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        A.theta_out[t] = bad ? NAN : theta;
+        if (A.iters) A.iters[t] = it;
+        if (A.status) A.status[t] = bad ? 1 : 0;
+    }
+}
+
+template <int MT>
+int launch(const MleArgs& a, size_t lds, hipStream_t stream)
+{
+    hipLaunchKernelGGL(mle_kernel<MT>, dim3((unsigned)a.T), dim3(MT), lds, stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int threads_for(int nmax)
+{
+    if (const char* e = getenv("LAGP_MLE_THREADS")) {
+        const int v = atoi(e);
+        if (v == 64 || v == 128 || v == 256) return v;
+    }
+    return nmax <= 24 ? 64 : 128;
+}
+
+}  // namespace
+
+size_t mle_lds_bytes(int nmax, int p, int threads)
+{
+    const size_t nm = (size_t)nmax;
+    return (nm * p + nm * (nm + 1) / 2 + nm * (nm - 1) / 2 + nm * PW + 6 * nm + (size_t)NRED * (threads / 64)) *
+           sizeof(double);
+}
+
+int mle_prepare(int32_t nmax, int p, size_t max_lds, std::string* err)
+{
+    if (mle_lds_bytes(nmax, p, 256) > max_lds) { *err = "local design too large for the likelihood kernel"; return -1; }
+    const void* k[3] = {(const void*)mle_kernel<64>, (const void*)mle_kernel<128>, (const void*)mle_kernel<256>};
+    for (const void* f : k)
+        if (!set_lds_limit(f, max_lds)) { *err = "cannot reserve LDS for the likelihood kernel"; return -2; }
+    return 0;
+}
+
+int mle_run(const MleArgs& a, size_t max_lds, hipStream_t stream, std::string* err)
+{
+    if (a.T == 0) return 0;
+    const int mt = threads_for(a.nmax);
+    const size_t lds = mle_lds_bytes(a.nmax, a.p, mt);
+    if (lds > max_lds) { *err = "local design too large for the likelihood kernel"; return -1; }
+    int rc = mt == 64 ? launch<64>(a, lds, stream) : mt == 128 ? launch<128>(a, lds, stream) : launch<256>(a, lds, stream);
+    if (rc) { *err = "likelihood kernel launch failed"; return rc; }
+    return 0;
+}
+
+}  // namespace lagp

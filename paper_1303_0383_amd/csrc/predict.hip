@@ -36,8 +36,9 @@ __global__ void __launch_bounds__(PT) local_predict_kernel(const double* __restr
                                                            const double* __restrict__ XX, int64_t T,
                                                            int64_t N, const int32_t* __restrict__ sel, int64_t sel_stride,
                                                            const int32_t* __restrict__ n_per, int n_all,
-                                                           double theta, double eta, double* mean, double* s2,
-                                                           int32_t* df, double* var, int8_t* status)
+                                                           double theta_all, const double* __restrict__ theta_per,
+                                                           double eta, double* mean, double* s2, int32_t* df,
+                                                           double* var, int8_t* status)
 {
     extern __shared__ double sm[];
     const int64_t t = blockIdx.x;
@@ -49,9 +50,11 @@ __global__ void __launch_bounds__(PT) local_predict_kernel(const double* __restr
     double* b1 = A + n * (n + 1) / 2;     // k_n(x), then L^{-1} k_n(x)
     double* b2 = b1 + n;                  // Y_n, then L^{-1} Y_n
     __shared__ int bad;
+    // A per-location lengthscale that is not a positive finite number fails the location.
+    const double theta = theta_per ? theta_per[t] : theta_all;
     const double rtheta = 1.0 / theta;
     const double* x = XX + t * p;
-    if (tid == 0) bad = 0;
+    if (tid == 0) bad = (theta > 0.0 && theta < INFINITY) ? 0 : 1;
     __syncthreads();
     // A usable design has n valid indices (the design kernel marks failures with -1).
     for (int a = tid; a < n; a += PT)
@@ -158,14 +161,15 @@ int predict_prepare(int32_t nmax, size_t max_lds, std::string* err)
 }
 
 int predict_run(const DeviceDesign& D, const double* XX, int64_t T, const int32_t* sel, int64_t sel_stride,
-                const int32_t* n_per, int32_t nmax, double theta, double eta, double* mean, double* s2,
-                int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream, std::string* err)
+                const int32_t* n_per, int32_t nmax, double theta, const double* theta_per, double eta, double* mean,
+                double* s2, int32_t* df, double* var, int8_t* status, size_t max_lds, hipStream_t stream,
+                std::string* err)
 {
     if (T == 0) return 0;
     const size_t lds = predict_lds_bytes(nmax);
     if (lds > max_lds) { *err = "local design too large for the prediction kernel"; return -1; }
     hipLaunchKernelGGL(local_predict_kernel, dim3((unsigned)T), dim3(PT), lds, stream, D.Xaos, D.y, D.p, XX, T, D.N, sel,
-                       sel_stride, n_per, nmax, theta, eta, mean, s2, df, var, status);
+                       sel_stride, n_per, nmax, theta, theta_per, eta, mean, s2, df, var, status);
     if (hipGetLastError() != hipSuccess) { *err = "prediction kernel launch failed"; return -2; }
     return 0;
 }

@@ -34,7 +34,8 @@ def gpu_predict(design, XX, n0, n, M, d, g, n_per=None, M_per=None, precision=0)
 
 
 def compare(X, y, XX, n0, n, M, d, g, res, idx=None, n_per=None, M_per=None):
-    """Compare GPU results `res` with the oracle at locations `idx` (default all).
+    """Compare GPU results `res` with the oracle at locations `idx` (default all);
+    d is one lengthscale or one per location.
 
     Returns a summary dict; raises AssertionError on a parity failure."""
     T = XX.shape[0]
@@ -45,7 +46,8 @@ def compare(X, y, XX, n0, n, M, d, g, res, idx=None, n_per=None, M_per=None):
     for t in idx:
         nt = int(n_per[t]) if n_per is not None else n
         mt = int(M_per[t]) if M_per is not None else M
-        rc, s_o, o, diag = oracle.local(X, y, XX[t], n0, nt, mt, d, g)
+        dt = float(d[t]) if np.ndim(d) else d      # per-location lengthscale
+        rc, s_o, o, diag = oracle.local(X, y, XX[t], n0, nt, mt, dt, g)
         s_g = res["sel"][t, :nt]
         if rc == oracle.NOTPD:
             assert res["status"][t] == 1, f"location {t}: oracle NOTPD, GPU status {res['status'][t]}"
@@ -60,7 +62,7 @@ def compare(X, y, XX, n0, n, M, d, g, res, idx=None, n_per=None, M_per=None):
             k = int(np.argmax(s_g != s_o))
             gap = (diag[k, 0] - diag[k, 1]) / diag[k, 0] if diag[k, 0] > 0 else 0.0
             assert gap < GAP_TOL, f"location {t}: selections differ at step {k} with gap {gap:.3e}"
-            rc2, s_r, o_r, diag_r = oracle.local(X, y, XX[t], n0, nt, mt, d, g, replay=s_g)
+            rc2, s_r, o_r, diag_r = oracle.local(X, y, XX[t], n0, nt, mt, dt, g, replay=s_g)
             assert rc2 == 0
             a1, ach = diag_r[n0:, 0], diag_r[n0:, 2]
             short = np.max((a1 - ach) / np.where(a1 > 0, a1, 1.0)) if len(a1) else 0.0

@@ -1,6 +1,6 @@
-"""Pins for the oracle's local lengthscale inference (eq gpk, eqs dl and d2l
-of SM Section 3, the Newton search of Section 3.1 and the two-stage scheme
-of Section 4.1).
+"""Pins for the oracle's local lengthscale inference (eq gpk of Section 2,
+eqs dl and d2l of SM Section 2, the Newton search of Section 3.2 and the
+two-stage scheme of Section 4.2).
 
 Each pin checks the oracle against something other than itself: the log
 likelihood evaluated by dense NumPy algebra (slogdet and solves), derivatives

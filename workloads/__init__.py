@@ -173,5 +173,13 @@ def c4_requests(num: int, rate_per_s: float, n0: int = 6):
 C4_PARAMS = dict(d=0.3, g=1e-5, n0=6)
 
 
+def mle_range(X: np.ndarray):
+    """Search interval for local lengthscale inference: from 1e-4 to the squared
+    diagonal of the design's bounding box (no lengthscale beyond the largest
+    squared distance in the design is identifiable)."""
+    span = X.max(axis=0) - X.min(axis=0)
+    return 1e-4, float(np.sum(span * span))
+
+
 def by_name(name: str, **kw) -> Workload:
     return {"c0": c0, "c1": c1, "c2": c2, "c3": c3}[name](**kw)
