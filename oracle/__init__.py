@@ -61,6 +61,7 @@ def _configure(L):
     L.lagp_oracle_alc.argtypes = [P, i32, P, P, i32, P, i64, f64, f64, P, P, P, P]
     L.lagp_oracle_alc_brute.argtypes = [P, i32, P, P, i32, P, i64, f64, f64, P]
     L.lagp_oracle_local.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, P, P]
+    L.lagp_oracle_local_ex.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, f64, P, P, P, P]
     L.lagp_oracle_batch.argtypes = [P, P, i64, i32, P, i64, i32, i32, i64, P, P, f64, f64,
                                     P, i64, P, P, i32]
     L.lagp_oracle_loglik.argtypes = [P, P, i32, P, i32, f64, f64, P]
@@ -68,7 +69,8 @@ def _configure(L):
     L.lagp_oracle_alc2.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, f64, f64, i32, f64, P, P, P, P]
     for f in (L.lagp_oracle_knn, L.lagp_oracle_predict, L.lagp_oracle_alc,
               L.lagp_oracle_alc_brute, L.lagp_oracle_local, L.lagp_oracle_batch,
-              L.lagp_oracle_max_threads, L.lagp_oracle_loglik, L.lagp_oracle_mle, L.lagp_oracle_alc2):
+              L.lagp_oracle_max_threads, L.lagp_oracle_loglik, L.lagp_oracle_mle, L.lagp_oracle_alc2,
+              L.lagp_oracle_local_ex):
         f.restype = C.c_int
 
 
@@ -135,6 +137,22 @@ def local(X, y, x, n0, n, M, d, g, replay=None, L=None):
     if rc < 0:
         raise ValueError(f"oracle local failed: {rc}")
     return rc, sel, out, diag
+
+
+def local_ex(X, y, x, n0, n, M, d, g, start=None, vratio=0.0, replay=None, L=None):
+    """lagp_oracle_local with a saved starting design (n0 = len(start)) and the
+    variance-ratio stopping rule.  Returns (rc, sel[n_used], n_used, out[5], diag[n,3])."""
+    X = _f64(X); y = _f64(y); x = _f64(x)
+    sel = np.empty(n, np.int32); out = np.empty(5); diag = np.empty((n, 3)); nu = np.zeros(1, np.int32)
+    st = None if start is None else _i32(start)
+    if st is not None:
+        n0 = len(st)
+    rp = None if replay is None else _i32(replay)
+    rc = (L or lib()).lagp_oracle_local_ex(_ptr(X), _ptr(y), X.shape[0], X.shape[1], _ptr(x), n0, n, M, d, g,
+                                           _ptr(rp), _ptr(st), vratio, _ptr(sel), _ptr(nu), _ptr(out), _ptr(diag))
+    if rc < 0:
+        raise ValueError(f"oracle local_ex failed: {rc}")
+    return rc, sel[:int(nu[0])], int(nu[0]), out, diag
 
 
 def batch(X, y, XX, n0, n, M, d, g, n_per=None, M_per=None, threads=0, L=None):

@@ -42,6 +42,11 @@
  * Section 4.2 with one repetition.  Every evaluation forms K^{-1} explicitly
  * from a fresh Cholesky factor.
  *
+ * Augmentation and stopping (Section 6's discussion): a saved design may
+ * replace the n0 nearest neighbours as the starting design, and the greedy
+ * search may stop once the best candidate's variance ratio v_j(x)/v_{j+1}(x)
+ * (V_j/V_{j+1} with psi cancelled) falls below a threshold.
+ *
  * Readings where the paper is silent (each is listed in the design notes):
  * distances are summed over coordinates left to right with no fused
  * multiply-add; nearest neighbours are ordered by (squared distance, index);
@@ -300,12 +305,24 @@ done:
  *                 of the oracle's own largest ALC.
  *
  * Returns ORACLE_OK, ORACLE_NOTPD (outputs NaN) or a negative error. */
-int lagp_oracle_local(const double *X, const double *y, int64_t N, int32_t p, const double *x,
-                      int32_t n0, int32_t n, int64_t M, double theta, double eta,
-                      const int32_t *replay, int32_t *sel, double *out, double *diag)
+/* The general form of lagp_oracle_local with the extensions of Section 6's
+ * discussion:
+ *   start (nullable): a saved local design of n0 indices that replaces the
+ *     n0 nearest neighbours, so the greedy search picks up where an earlier
+ *     one left off (augmentation); every start index must be one of x's M
+ *     candidates and appear once, else ORACLE_EINVAL;
+ *   vratio: when > 0, stop before greedy step j (j >= n0) once the best
+ *     candidate's variance ratio v_j(x) / v_{j+1}(x) = v_j(x) / (v_j(x) -
+ *     ALC_j) is below vratio (psi cancels in the ratio V_j / V_{j+1}), so
+ *     the design has n_used <= n points;
+ *   n_used (nullable) receives the final design size. */
+int lagp_oracle_local_ex(const double *X, const double *y, int64_t N, int32_t p, const double *x,
+                         int32_t n0, int32_t n, int64_t M, double theta, double eta,
+                         const int32_t *replay, const int32_t *start, double vratio, int32_t *sel,
+                         int32_t *n_used, double *out, double *diag)
 {
     if (N < 1 || p < 1 || n0 < 1 || n0 > n || (int64_t)n > M || M > N || !(theta > 0.0) ||
-        !(eta >= 0.0))
+        !(eta >= 0.0) || !(vratio >= 0.0))
         return ORACLE_EINVAL;
     int32_t *C = (int32_t *)malloc((size_t)M * sizeof(int32_t));
     char *used = (char *)calloc((size_t)M, 1);
@@ -321,12 +338,18 @@ int lagp_oracle_local(const double *X, const double *y, int64_t N, int32_t p, co
     if (rc != ORACLE_OK) goto done;
 
     for (int j = 0; j < n0; j++) {
-        if (replay && replay[j] != C[j]) { rc = ORACLE_EINVAL; goto done; }
-        sel[j] = C[j];
-        used[j] = 1;
+        int64_t ci = j;
+        if (start) {   /* the saved design's j-th point, found among the candidates */
+            for (ci = 0; ci < M && C[ci] != start[j]; ci++) {}
+            if (ci == M || used[ci]) { rc = ORACLE_EINVAL; goto done; }
+        }
+        if (replay && replay[j] != C[ci]) { rc = ORACLE_EINVAL; goto done; }
+        sel[j] = C[ci];
+        used[ci] = 1;
         if (diag) diag[3 * j] = diag[3 * j + 1] = diag[3 * j + 2] = NAN;
     }
 
+    int32_t nu = n;
     for (int j = n0; j < n; j++) {
         /* K_j and its Cholesky factor, from scratch. */
         design_cov(X, p, sel, j, theta, eta, K);
@@ -354,6 +377,11 @@ int lagp_oracle_local(const double *X, const double *y, int64_t N, int32_t p, co
             if (replay && C[ci] == replay[j]) { follow = ci; a_follow = alc; }
         }
         if (best < 0 || a1 == -INFINITY) { rc = ORACLE_NOTPD; break; }
+        if (vratio > 0.0) {
+            const double vx = (1.0 + eta) - dot(wx, wx, j);
+            const double vnext = vx - a1;
+            if (vnext > 0.0 && vx / vnext < vratio) { nu = j; break; }
+        }
         int64_t take = best;
         if (replay) {
             if (follow < 0) { rc = ORACLE_EINVAL; goto done; }
@@ -368,13 +396,22 @@ int lagp_oracle_local(const double *X, const double *y, int64_t N, int32_t p, co
         used[take] = 1;
     }
 
-    if (rc == ORACLE_OK) rc = lagp_oracle_predict(X, y, p, x, sel, n, theta, eta, out);
+    if (rc == ORACLE_OK) rc = lagp_oracle_predict(X, y, p, x, sel, nu, theta, eta, out);
     if (rc == ORACLE_NOTPD) {
         for (int i = 0; i < 5; i++) out[i] = NAN;
     }
+    for (int j = nu; j < n; j++) sel[j] = -1;
+    if (n_used) *n_used = nu;
 done:
     free(C); free(used); free(K); free(L); free(kx); free(wx); free(kc); free(wc);
     return rc;
+}
+
+int lagp_oracle_local(const double *X, const double *y, int64_t N, int32_t p, const double *x,
+                      int32_t n0, int32_t n, int64_t M, double theta, double eta,
+                      const int32_t *replay, int32_t *sel, double *out, double *diag)
+{
+    return lagp_oracle_local_ex(X, y, N, p, x, n0, n, M, theta, eta, replay, NULL, 0.0, sel, NULL, out, diag);
 }
 
 /* Independent local designs over T predictive locations (Section 4.1),
