@@ -61,6 +61,8 @@ def _configure(L):
     L.lagp_oracle_alc.argtypes = [P, i32, P, P, i32, P, i64, f64, f64, P, P, P, P]
     L.lagp_oracle_alc_brute.argtypes = [P, i32, P, P, i32, P, i64, f64, f64, P]
     L.lagp_oracle_local.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, P, P]
+    L.lagp_oracle_mspe.argtypes = [P, P, i32, P, P, i32, P, i32, f64, f64, P, P, P]
+    L.lagp_oracle_mspe_local.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, P]
     L.lagp_oracle_local_ex.argtypes = [P, P, i64, i32, P, i32, i32, i64, f64, f64, P, P, f64, P, P, P, P]
     L.lagp_oracle_batch.argtypes = [P, P, i64, i32, P, i64, i32, i32, i64, P, P, f64, f64,
                                     P, i64, P, P, i32]
@@ -70,7 +72,7 @@ def _configure(L):
     for f in (L.lagp_oracle_knn, L.lagp_oracle_predict, L.lagp_oracle_alc,
               L.lagp_oracle_alc_brute, L.lagp_oracle_local, L.lagp_oracle_batch,
               L.lagp_oracle_max_threads, L.lagp_oracle_loglik, L.lagp_oracle_mle, L.lagp_oracle_alc2,
-              L.lagp_oracle_local_ex):
+              L.lagp_oracle_local_ex, L.lagp_oracle_mspe, L.lagp_oracle_mspe_local):
         f.restype = C.c_int
 
 
@@ -153,6 +155,30 @@ def local_ex(X, y, x, n0, n, M, d, g, start=None, vratio=0.0, replay=None, L=Non
     if rc < 0:
         raise ValueError(f"oracle local_ex failed: {rc}")
     return rc, sel[:int(nu[0])], int(nu[0]), out, diag
+
+
+def mspe(X, y, x, D, cand, d, g, L=None):
+    """MSPE criterion J(c) of each candidate for the design D (eq mspe).
+    Returns (rc, J, parts[ncand, 5] = {V_j(x|c), dmu_c, dV_c, V_c, G},
+    scal = {F_j, dmu_x, psi, q, v_j(x)})."""
+    X = _f64(X); y = _f64(y); x = _f64(x); D = _i32(D); cand = _i32(cand)
+    J = np.empty(len(cand)); parts = np.empty((len(cand), 5)); scal = np.empty(5)
+    rc = (L or lib()).lagp_oracle_mspe(_ptr(X), _ptr(y), X.shape[1], _ptr(x), _ptr(D), len(D), _ptr(cand), len(cand),
+                                       d, g, _ptr(J), _ptr(parts), _ptr(scal))
+    if rc < 0:
+        raise ValueError(f"oracle mspe failed: {rc}")
+    return rc, J, parts, scal
+
+
+def mspe_local(X, y, x, n0, n, M, d, g, L=None):
+    """Greedy MSPE design + prediction.  Returns (rc, sel[n], out[5], diag[n, 2])."""
+    X = _f64(X); y = _f64(y); x = _f64(x)
+    sel = np.empty(n, np.int32); out = np.empty(5); diag = np.empty((n, 2))
+    rc = (L or lib()).lagp_oracle_mspe_local(_ptr(X), _ptr(y), X.shape[0], X.shape[1], _ptr(x), n0, n, M, d, g,
+                                             _ptr(sel), _ptr(out), _ptr(diag))
+    if rc < 0:
+        raise ValueError(f"oracle mspe_local failed: {rc}")
+    return rc, sel, out, diag
 
 
 def batch(X, y, XX, n0, n, M, d, g, n_per=None, M_per=None, threads=0, L=None):

@@ -42,6 +42,11 @@
  * Section 4.2 with one repetition.  Every evaluation forms K^{-1} explicitly
  * from a fresh Cholesky factor.
  *
+ * MSPE criterion (Section 3.1, eq mspe): the alternative greedy rule that
+ * minimises the approximate mean-squared predictive error, which adds to the
+ * reduced variance the theta-uncertainty term (dmu/dtheta)^2 / G with the
+ * expected Fisher information G, at fixed theta.
+ *
  * Augmentation and stopping (Section 6's discussion): a saved design may
  * replace the n0 nearest neighbours as the starting design, and the greedy
  * search may stop once the best candidate's variance ratio v_j(x)/v_{j+1}(x)
@@ -598,6 +603,187 @@ int lagp_oracle_alc2(const double *X, const double *y, int64_t N, int32_t p, con
     rc = lagp_oracle_mle(X, y, p, sel2, n, thetas[0], eta, tmin, tmax, maxit, tol, &thetas[1], &its);
     if (rc != ORACLE_OK) return rc;
     return lagp_oracle_predict(X, y, p, x, sel2, n, thetas[1], eta, out5);
+}
+
+/* ---- MSPE criterion (Section 3.1, eq mspe; expressions of Section 3.1 and
+ * SM Section 2), at fixed theta as Section 3.2 recommends.
+ *
+ * For the design D (j >= 3 points) and each candidate c:
+ *   J(c) = V_j(x|c) + (dmu_j(x)/dtheta)^2 / G_{j+1}(c),
+ *   V_j(x|c)   = psi/(j-2) * v_{j+1}(x|c),  v_{j+1}(x|c) = v_j(x) - cov_j(x,c)^2 / v_j(c),
+ *   dmu_j(z)   = (kd_j(z) - Kd K^{-1} k_j(z))' K^{-1} Y          (z = x or c),
+ *   G_{j+1}(c) = F_j + dV_j(c)^2 / (2 V_j(c)^2) + dmu_j(c)^2 / V_j(c),
+ *   V_j(c)     = psi/(j-2) * v_j(c),  F_j = -l''(theta) of the design (eq d2l),
+ *   dV_j(c)    = d V_j(c) / dtheta = [-q v_j(c) - psi (2 kd_j(c)'K^{-1}k_j(c)
+ *                                      - k_j(c)'K^{-1} Kd K^{-1} k_j(c))] / (j-2),
+ * with q = Y'K^{-1} Kd K^{-1} Y = -dpsi/dtheta and kd_j(z) the derivatives of
+ * K(x_i, z) in theta.  (The printed dV carries +q; the derivative of
+ * psi v / (j-2) has -q, which is the reading taken.)  Everything is formed
+ * from an explicit K^{-1} of a fresh Cholesky factor.  A candidate with
+ * v_j(c) <= 0 scores +infinity.
+ *   J[ncand]; parts (nullable) ncand x 5 = {V_j(x|c), dmu_j(c), dV_j(c), V_j(c), G};
+ *   scal (nullable) = {F_j, dmu_j(x), psi, q, v_j(x)}. */
+int lagp_oracle_mspe(const double *X, const double *y, int32_t p, const double *x, const int32_t *D, int32_t j,
+                     const int32_t *cand, int32_t ncand, double theta, double eta, double *J, double *parts,
+                     double *scal)
+{
+    if (j < 3 || ncand < 0 || !(theta > 0.0)) return ORACLE_EINVAL;
+    double l3[3];
+    int rc = lagp_oracle_loglik(X, y, p, D, j, theta, eta, l3);
+    if (rc != ORACLE_OK) return rc;
+    const size_t jj = (size_t)j * j;
+    double *K = (double *)malloc(jj * sizeof(double));
+    double *L = (double *)malloc(jj * sizeof(double));
+    double *Ki = (double *)malloc(jj * sizeof(double));
+    double *Kd = (double *)malloc(jj * sizeof(double));
+    double *e = (double *)malloc((size_t)j * sizeof(double));
+    double *col = (double *)malloc((size_t)j * sizeof(double));
+    double *Yd = (double *)malloc((size_t)j * sizeof(double));
+    double *al = (double *)malloc((size_t)j * sizeof(double));    /* K^{-1} Y */
+    double *Kal = (double *)malloc((size_t)j * sizeof(double));   /* Kd K^{-1} Y */
+    double *k = (double *)malloc((size_t)j * sizeof(double));
+    double *kd = (double *)malloc((size_t)j * sizeof(double));
+    double *kt = (double *)malloc((size_t)j * sizeof(double));    /* K^{-1} k */
+    double *Kkt = (double *)malloc((size_t)j * sizeof(double));   /* Kd K^{-1} k */
+    double *Li = (double *)calloc(jj, sizeof(double));
+    if (!K || !L || !Ki || !Kd || !e || !col || !Yd || !al || !Kal || !k || !kd || !kt || !Kkt || !Li) {
+        rc = ORACLE_ENOMEM;
+        goto done;
+    }
+    design_cov(X, p, D, j, theta, eta, K);
+    for (int a = 0; a < j; a++) {
+        Yd[a] = y[D[a]];
+        for (int b = 0; b < j; b++) {
+            const double d2 = sqdist(X + (size_t)D[a] * p, X + (size_t)D[b] * p, p);
+            Kd[(size_t)a * j + b] = (a == b) ? 0.0 : K[(size_t)a * j + b] * d2 / (theta * theta);
+        }
+    }
+    if (cholesky(K, j, L) != 0) { rc = ORACLE_NOTPD; goto done; }
+    for (int c = 0; c < j; c++) {
+        for (int a = 0; a < j; a++) e[a] = (a == c) ? 1.0 : 0.0;
+        forward_solve(L, j, e, col);
+        for (int a = 0; a < j; a++) Li[(size_t)a * j + c] = col[a];
+    }
+    for (int a = 0; a < j; a++)
+        for (int b = 0; b < j; b++) {
+            double s = 0.0;
+            for (int m = 0; m < j; m++) s += Li[(size_t)m * j + a] * Li[(size_t)m * j + b];
+            Ki[(size_t)a * j + b] = s;
+        }
+    for (int a = 0; a < j; a++) al[a] = dot(Ki + (size_t)a * j, Yd, j);
+    for (int a = 0; a < j; a++) Kal[a] = dot(Kd + (size_t)a * j, al, j);
+    {
+        const double psi = dot(Yd, al, j);
+        const double q = dot(al, Kal, j);
+        const double F = -l3[2];
+        const double sc = psi / (j - 2);
+        /* the predictive location */
+        for (int a = 0; a < j; a++) {
+            const double d2 = sqdist(X + (size_t)D[a] * p, x, p);
+            k[a] = exp(-d2 / theta);
+            kd[a] = k[a] * d2 / (theta * theta);
+        }
+        for (int a = 0; a < j; a++) kt[a] = dot(Ki + (size_t)a * j, k, j);
+        const double vx = (1.0 + eta) - dot(k, kt, j);
+        const double dmux = dot(kd, al, j) - dot(kt, Kal, j);
+        double *kxs = (double *)malloc((size_t)j * sizeof(double));   /* k_j(x) */
+        if (!kxs) { rc = ORACLE_ENOMEM; goto done; }
+        memcpy(kxs, k, (size_t)j * sizeof(double));
+        for (int ci = 0; ci < ncand; ci++) {
+            const double *xc = X + (size_t)cand[ci] * p;
+            for (int a = 0; a < j; a++) {
+                const double d2 = sqdist(X + (size_t)D[a] * p, xc, p);
+                k[a] = exp(-d2 / theta);
+                kd[a] = k[a] * d2 / (theta * theta);
+            }
+            for (int a = 0; a < j; a++) kt[a] = dot(Ki + (size_t)a * j, k, j);
+            for (int a = 0; a < j; a++) Kkt[a] = dot(Kd + (size_t)a * j, kt, j);
+            const double vc = (1.0 + eta) - dot(k, kt, j);
+            const double cov = exp(-sqdist(x, xc, p) / theta) - dot(kxs, kt, j);
+            double Jc = INFINITY, vxc = NAN, dmuc = NAN, dVc = NAN, Vc = NAN, G = NAN;
+            if (vc > 0.0) {
+                vxc = sc * (vx - cov * cov / vc);
+                Vc = sc * vc;
+                dmuc = dot(kd, al, j) - dot(kt, Kal, j);
+                dVc = (-q * vc - psi * (2.0 * dot(kd, kt, j) - dot(kt, Kkt, j))) / (j - 2);
+                G = F + dVc * dVc / (2.0 * Vc * Vc) + dmuc * dmuc / Vc;
+                Jc = vxc + dmux * dmux / G;
+            }
+            J[ci] = Jc;
+            if (parts) {
+                parts[5 * ci] = vxc;
+                parts[5 * ci + 1] = dmuc;
+                parts[5 * ci + 2] = dVc;
+                parts[5 * ci + 3] = Vc;
+                parts[5 * ci + 4] = G;
+            }
+        }
+        if (scal) {
+            scal[0] = F;
+            scal[1] = dmux;
+            scal[2] = psi;
+            scal[3] = q;
+            scal[4] = vx;
+        }
+        free(kxs);
+    }
+done:
+    free(K); free(L); free(Ki); free(Kd); free(e); free(col); free(Yd); free(al); free(Kal);
+    free(k); free(kd); free(kt); free(Kkt); free(Li);
+    return rc;
+}
+
+/* Greedy MSPE local design (Section 3.1): from the n0 >= 3 nearest
+ * neighbours, add the candidate with the smallest J(c) until n points (ties
+ * to the smaller design index), then predict as lagp_oracle_local does.
+ * diag (nullable, n x 2): the smallest and second smallest J per step. */
+int lagp_oracle_mspe_local(const double *X, const double *y, int64_t N, int32_t p, const double *x, int32_t n0,
+                           int32_t n, int64_t M, double theta, double eta, int32_t *sel, double *out, double *diag)
+{
+    if (N < 1 || p < 1 || n0 < 3 || n0 > n || (int64_t)n > M || M > N || !(theta > 0.0) || !(eta >= 0.0))
+        return ORACLE_EINVAL;
+    int32_t *C = (int32_t *)malloc((size_t)M * sizeof(int32_t));
+    int32_t *live = (int32_t *)malloc((size_t)M * sizeof(int32_t));
+    char *used = (char *)calloc((size_t)M, 1);
+    double *J = (double *)malloc((size_t)M * sizeof(double));
+    int rc = ORACLE_OK;
+    if (!C || !live || !used || !J) { rc = ORACLE_ENOMEM; goto done; }
+    rc = lagp_oracle_knn(X, N, p, x, M, C, NULL);
+    if (rc != ORACLE_OK) goto done;
+    for (int j = 0; j < n0; j++) {
+        sel[j] = C[j];
+        used[j] = 1;
+        if (diag) diag[2 * j] = diag[2 * j + 1] = NAN;
+    }
+    for (int j = n0; j < n; j++) {
+        int32_t nl = 0;
+        for (int64_t ci = 0; ci < M; ci++)
+            if (!used[ci]) live[nl++] = C[ci];
+        rc = lagp_oracle_mspe(X, y, p, x, sel, j, live, nl, theta, eta, J, NULL, NULL);
+        if (rc != ORACLE_OK) break;
+        double j1 = INFINITY, j2 = INFINITY;
+        int32_t best = -1;
+        for (int32_t a = 0; a < nl; a++) {
+            if (best < 0 || J[a] < j1 || (J[a] == j1 && live[a] < live[best])) {
+                j2 = j1;
+                j1 = J[a];
+                best = a;
+            } else if (J[a] < j2) {
+                j2 = J[a];
+            }
+        }
+        if (best < 0 || j1 == INFINITY) { rc = ORACLE_NOTPD; break; }
+        if (diag) { diag[2 * j] = j1; diag[2 * j + 1] = j2; }
+        sel[j] = live[best];
+        for (int64_t ci = 0; ci < M; ci++)
+            if (C[ci] == live[best]) used[ci] = 1;
+    }
+    if (rc == ORACLE_OK) rc = lagp_oracle_predict(X, y, p, x, sel, n, theta, eta, out);
+    if (rc == ORACLE_NOTPD)
+        for (int i = 0; i < 5; i++) out[i] = NAN;
+done:
+    free(C); free(live); free(used); free(J);
+    return rc;
 }
 
 int lagp_oracle_max_threads(void)
