@@ -285,7 +285,7 @@ def main() -> int:
             nts = [int(nps[i]) if nps is not None else w.n for i in range(len(idx))]
             same = all(np.array_equal(r1["sel"][i, :nts[i]], res["sel"][t, :nts[i]]) for i, t in enumerate(idx))
             summ = compare(w.X, w.y, w.XX[idx], w.n0, w.n, w.ncand, th1[idx], w.g, r1, n_per=nps, M_per=mps)
-            ok = same and worst_th <= 1e-8 and worst_mu <= 1e-9
+            ok = bool(same and worst_th <= 1e-8 and worst_mu <= 1e-9)
             result["parity"] = {"locations": len(idx), "ok": ok, "kind": "stagewise",
                                 "theta2_rel": float(f"{worst_th:.3e}"), "mean_rel": float(f"{worst_mu:.3e}"),
                                 "second_designs": {k: (float(f"{v:.3e}") if isinstance(v, float) else v)

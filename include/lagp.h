@@ -58,7 +58,8 @@ typedef enum {
 } lagp_status;
 
 /* Per-location status codes written to the optional `status` output. */
-enum { LAGP_LOC_OK = 0, LAGP_LOC_NOTPD = 1 };
+enum { LAGP_LOC_OK = 0, LAGP_LOC_NOTPD = 1, LAGP_LOC_NOTCAND = 2 /* a saved starting-design index is not
+                                                                     among the location's candidates, or repeats */ };
 
 /* Precision of the ALC scoring contraction.  The variance v_j(c), covariance
  * cov_j(x,c), the factor update and the final prediction are FP64 in every
@@ -123,6 +124,32 @@ int lagp_predict(const lagp_design *design, const double *XX, int64_t T, const l
                  const int32_t *n_per, const int32_t *ncand_per, double *mean, double *s2,
                  int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
                  void *stream);
+
+/* Options of lagp_predict_ex (Section 6's discussion of augmenting saved
+ * local designs and of a stopping rule; Section 4.2's per-location
+ * lengthscales).  Zero-initialise and set what is used. */
+typedef struct {
+    const double *d_per;     /* optional device double[T]: lengthscale per location (replaces params->d) */
+    const int32_t *start;    /* optional device int32 T x start_stride: saved local designs; location t's
+                                first start_n[t] (or params->n0) entries replace its n0 nearest
+                                neighbours as the starting design, so the greedy search picks up
+                                where an earlier one left off.  Each index must be one of the
+                                location's ncand candidates and appear once, else the location
+                                gets status LAGP_LOC_NOTCAND and NaN outputs */
+    int64_t start_stride;    /* >= the largest starting-design size                              */
+    const int32_t *start_n;  /* optional device int32[T]: starting-design sizes, 1 <= start_n <= n */
+    double vratio;           /* 0: off.  Otherwise stop the greedy search before step j once the
+                                best candidate's variance ratio v_j(x) / (v_j(x) - ALC_j), i.e.
+                                V_j(x) / V_{j+1}(x) with psi cancelled, is below vratio; the
+                                design then has df[t] <= n points (df is required; sel entries
+                                past df[t] are -1) */
+} lagp_options;
+
+/* lagp_predict with the options above; opts may be NULL. */
+int lagp_predict_ex(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
+                    const lagp_options *opts, const int32_t *n_per, const int32_t *ncand_per, double *mean,
+                    double *s2, int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
+                    void *stream);
 
 /* lagp_predict with a lengthscale per location (Section 4.2: after local
  * inference each location has its own theta_x, possibly smoothed over the

@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblagp.so")
 
 LAGP_OK, LAGP_E_INVAL, LAGP_E_NOMEM, LAGP_E_NODEVICE, LAGP_E_HIP, LAGP_E_BUDGET, LAGP_E_NOTPD = 0, -1, -2, -3, -4, -5, -6
-LAGP_LOC_OK, LAGP_LOC_NOTPD = 0, 1
+LAGP_LOC_OK, LAGP_LOC_NOTPD, LAGP_LOC_NOTCAND = 0, 1, 2
 LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32 = 0, 1
 LAGP_PTR_HOST, LAGP_STRICT = 1, 2
 LAGP_BATCH_SEL, LAGP_BATCH_STATUS = 1, 2
@@ -42,6 +42,11 @@ class lagp_params(C.Structure):
                 ("g", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32)]
 
 
+class lagp_options(C.Structure):
+    _fields_ = [("d_per", C.c_void_p), ("start", C.c_void_p), ("start_stride", C.c_int64),
+                ("start_n", C.c_void_p), ("vratio", C.c_double)]
+
+
 class lagp_mle_params(C.Structure):
     _fields_ = [("tmin", C.c_double), ("tmax", C.c_double), ("maxit", C.c_int32), ("tol", C.c_double)]
 
@@ -53,6 +58,8 @@ _lib.lagp_design_destroy.restype = None
 _lib.lagp_knn.argtypes = [_P, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]
 _lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P,
                               C.c_int64, _P, _P]
+_lib.lagp_predict_ex.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_options), _P, _P, _P, _P,
+                                _P, _P, _P, C.c_int64, _P, _P]
 _lib.lagp_predict_theta.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P, _P,
                                    C.c_int64, _P, _P]
 _lib.lagp_predict_alc2.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_mle_params), _P, _P, _P,
@@ -84,7 +91,7 @@ for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_byt
            "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
            "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant",
            "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats", "lagp_predict_theta",
-           "lagp_predict_alc2", "lagp_mle"):
+           "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -163,6 +170,13 @@ def lagp_predict(design, XX, T: int, params: lagp_params, n_per, ncand_per, mean
     _check(_lib.lagp_predict(design, _ptr(XX), T, C.byref(params), _ptr(n_per), _ptr(ncand_per), _ptr(mean),
                              _ptr(s2), _ptr(df), _ptr(var), _ptr(sel), sel_stride, _ptr(status),
                              _stream(stream)))
+
+
+def lagp_predict_ex(design, XX, T: int, params: lagp_params, opts, n_per, ncand_per, mean, s2, df, var, sel,
+                    sel_stride: int, status, stream=None) -> None:
+    _check(_lib.lagp_predict_ex(design, _ptr(XX), T, C.byref(params), None if opts is None else C.byref(opts),
+                                _ptr(n_per), _ptr(ncand_per), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel),
+                                sel_stride, _ptr(status), _stream(stream)))
 
 
 def lagp_predict_theta(design, XX, T: int, params: lagp_params, d_per, n_per, ncand_per, mean, s2, df, var, sel,
@@ -392,16 +406,23 @@ class Design:
 
     def predict(self, XX, n0: int, n: int, ncand: int, d: float, g: float, n_per=None, ncand_per=None,
                 precision: int = LAGP_PREC_FP64, strict: bool = False, out: Optional[Prediction] = None,
-                d_per=None, stream=None) -> Prediction:
+                d_per=None, start=None, start_n=None, vratio: float = 0.0, stream=None) -> Prediction:
         """Greedy ALC designs and prediction; d_per (device float64[T]) gives each
-        location its own lengthscale."""
+        location its own lengthscale; start (device int32 T x k) saved designs to
+        augment (their first start_n[t], or n0, entries); vratio > 0 the
+        variance-ratio stopping rule (df then holds each design's size)."""
         XX = XX.contiguous()
         T = XX.shape[0]
         nmax = int(n_per.max().item()) if (n_per is not None and T) else n
         if out is None:
             out = _outputs(T, nmax, XX.device)
         prm = lagp_params(n0, n, ncand, d, g, precision, LAGP_STRICT if strict else 0)
-        if d_per is None:
+        if start is not None or vratio != 0.0:
+            st = None if start is None else start.contiguous()
+            opts = lagp_options(_ptr(d_per), _ptr(st), 0 if st is None else st.shape[1], _ptr(start_n), vratio)
+            lagp_predict_ex(self._h, XX, T, prm, opts, n_per, ncand_per, out.mean, out.s2, out.df, out.var,
+                            out.sel, out.sel.shape[1], out.status, stream)
+        elif d_per is None:
             lagp_predict(self._h, XX, T, prm, n_per, ncand_per, out.mean, out.s2, out.df, out.var, out.sel,
                          out.sel.shape[1], out.status, stream)
         else:

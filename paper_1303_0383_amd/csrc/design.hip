@@ -124,6 +124,10 @@ int design_run(const DeviceDesign& D, const DesignLaunch& L, const DesignPlan& p
     a.M = L.M;
     a.theta = L.theta;
     a.theta_per = L.theta_per;
+    a.start = L.start;
+    a.start_stride = L.start_stride;
+    a.start_n = L.start_n;
+    a.vratio = L.vratio;
     a.eta = L.eta;
     a.mean = L.mean;
     a.s2 = L.s2;

@@ -56,6 +56,10 @@ struct DesignArgs {
     int n0, n, M;
     double theta, eta;
     const double* theta_per;  // nullable: per-location lengthscale (replaces theta)
+    const int32_t* start;     // nullable: saved starting designs, T x start_stride (replace the n0 nearest)
+    int64_t start_stride;
+    const int32_t* start_n;   // nullable: per-location starting-design size (else n0)
+    double vratio;            // > 0: stop once v_j(x) / v_{j+1}(x) falls below it
     double* mean;
     double* s2;
     int32_t* df;
@@ -344,11 +348,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         int koff[CPT];
 #pragma unroll
         for (int k = 0; k < CPT; ++k) koff[k] = (k < kact ? k : kact - 1) * DT;
-        const int n0 = A.n0;
+        const int n0 = (A.start && A.start_n) ? A.start_n[t] : A.n0;
         const int32_t* cand = A.cand + t * A.cand_stride;
         for (int k = tid; k < p; k += DT) xl[k] = A.XX[t * p + k];
         // ws, wx, uu are zero beyond the current step: padded terms subtract an exact 0.
         for (int l = tid; l < nmax; l += DT) { ws[l] = 0.0; wx[l] = 0.0; uu[l] = 0.0; }
+        if (tid == 0) misc[1] = one_eta;   // v_j(x), tracked for the stopping rule
         if (A.sel)
             for (int i = tid; i < n; i += DT) A.sel[t * A.sel_stride + i] = -1;
         __syncthreads();
@@ -402,8 +407,29 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             }
         }
 
-        // ---- starting design: the n0 nearest candidates, by (distance, index)
-        {
+        // ---- starting design: a saved design located among the candidates, or
+        //      the n0 nearest candidates by (distance, index)
+        if (A.start) {
+            const int32_t* st = A.start + t * A.start_stride;
+            for (int r = tid; r < n0; r += DT) forced[r] = -1;
+            __syncthreads();
+            uint32_t hit = 0;
+            for (int r = 0; r < n0; ++r) {
+                const int want = st[r];
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    if (tid + k * DT < M && ci[k] == want) {
+                        forced[r] = ((hit >> k) & 1u) ? -2 : tid + k * DT;   // -2: repeated index
+                        hit |= 1u << k;
+                    }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int bad = 0;
+                for (int r = 0; r < n0; ++r) bad |= forced[r] < 0;
+                ctl[2] = bad;
+            }
+        } else {
             uint32_t taken = chosen;
             for (int r = 0; r < n0; ++r) {
                 double bd = INFINITY;
@@ -427,8 +453,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         __syncthreads();
 
         // ---- greedy steps
+        const int badstart = A.start ? ctl[2] : 0;
         int s_next = -1;
-        int notpd = theta_ok ? 0 : 1;
+        int notpd = (theta_ok && !badstart) ? 0 : 1;
+        int nuse = n;   // design size reached (the stopping rule may end the search early)
         for (int i = 0; i < n && !notpd; ++i) {
             const int s = (i < n0) ? forced[i] : s_next;
             if (s < 0 || s >= M) { notpd = 1; break; }
@@ -663,6 +691,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 wx[i] = rx;
                 uu[i] = div_by(ay, delta, rdelta);
                 if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
+                misc[1] -= rx * rx;
             }
             double r[CPT];
 #pragma unroll
@@ -721,6 +750,13 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 for (int w = 1; w < DWAVES; ++w) pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
                 if (bs < 0 || bv == -INFINITY) { notpd = 1; break; }
                 s_next = bs;
+                // Stopping rule: the best candidate would shrink v(x) by less
+                // than the factor vratio (v_{i+1}(x) was published before B2).
+                if (A.vratio > 0.0) {
+                    const double vx = misc[1];
+                    const double vnext = vx - bv;
+                    if (vnext > 0.0 && vx / vnext < A.vratio) { nuse = i + 1; break; }
+                }
             }
         }
 
@@ -733,22 +769,24 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 mean = s2v = var = NAN;
             } else {
                 double m = 0.0, ps = 0.0, q = 0.0;
-                for (int l = 0; l < n; ++l) {
+                for (int l = 0; l < nuse; ++l) {
                     m += wx[l] * uu[l];
                     ps += uu[l] * uu[l];
                     q += wx[l] * wx[l];
                 }
                 const double vxn = one_eta - q;
                 mean = m;
-                s2v = ps * vxn / n;
-                var = n > 2 ? ps * vxn / (n - 2) : NAN;
+                s2v = ps * vxn / nuse;
+                var = nuse > 2 ? ps * vxn / (nuse - 2) : NAN;
             }
             A.mean[t] = mean;
             A.s2[t] = s2v;
             if (A.var) A.var[t] = var;
-            if (A.df) A.df[t] = n;
-            if (A.status) A.status[t] = notpd ? 1 : 0;
+            if (A.df) A.df[t] = nuse;
+            if (A.status) A.status[t] = badstart ? 2 : notpd ? 1 : 0;
         }
+        // the mixed mode's FP64 prediction reads the design size reached
+        if (MIX && tid == 0 && A.vratio > 0.0 && A.df) A.df[t] = nuse;
         __syncthreads();
     }
 }

@@ -455,7 +455,7 @@ int plan_alc2(const lagp_design* d, const lagp_mle_params* mle, bool have_sel, P
     int rc = check_mle_params(mle);
     if (rc) return rc;
     if (P->nmin < 2) return fail(LAGP_E_INVAL, "the two-stage scheme needs n >= 2 at every location");
-    if (lagp::mle_lds_bytes(P->nmax, d->dev.p, 256) > d->max_lds)
+    if (lagp::mle_lds_bytes(P->nmax, d->dev.p, 512) > d->max_lds)
         return fail(LAGP_E_INVAL, "n too large for the likelihood kernel");
     if (lagp::predict_lds_bytes(P->nmax) > d->max_lds) return fail(LAGP_E_INVAL, "n too large for the prediction kernel");
     P->alc2 = true;
@@ -497,7 +497,9 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     }
     if (P.mix) {
-        int r = lagp::predict_run(d->dev, L.XX, c.T, L.sel, L.sel_stride, L.n_per, c.nmax, L.theta, L.theta_per, L.eta,
+        // with the stopping rule the design kernel has written the size reached into df
+        const int32_t* sizes = L.vratio > 0.0 ? L.df : L.n_per;
+        int r = lagp::predict_run(d->dev, L.XX, c.T, L.sel, L.sel_stride, sizes, c.nmax, L.theta, L.theta_per, L.eta,
                                   L.mean, L.s2, L.df, L.var, L.status, d->max_lds, s, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
         // FP32 ranking can lose positive definiteness where FP64 keeps it
@@ -575,6 +577,12 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
         L.n0 = P.prm.n0;
         L.theta = P.prm.d;
         L.theta_per = d_per ? d_per + c.t0 : nullptr;
+        if (th && th->start) {
+            L.start = th->start + c.t0 * th->start_stride;
+            L.start_stride = th->start_stride;
+            L.start_n = th->start_n ? th->start_n + c.t0 : nullptr;
+        }
+        L.vratio = th ? th->vratio : 0.0;
         L.eta = P.prm.g;
         L.mean = o.mean + c.t0;
         L.s2 = o.s2 + c.t0;
@@ -712,9 +720,12 @@ static int run_predict(const lagp_design* design, const double* XX, int64_t T, c
     if (!XX || !mean || !s2) return fail(LAGP_E_INVAL, "XX, mean and s2 are required");
     int rc = check_device(design);
     if (rc) return rc;
-    const void* devptrs[] = {XX, n_per, ncand_per, th.d_per, th.d1, th.d2};
+    const void* devptrs[] = {XX, n_per, ncand_per, th.d_per, th.d1, th.d2, th.start, th.start_n};
     for (const void* q : devptrs)
         if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
+    if (!(th.vratio >= 0.0) || !isfinite(th.vratio)) return fail(LAGP_E_INVAL, "vratio must be >= 0 and finite");
+    if (th.vratio > 0.0 && !df) return fail(LAGP_E_INVAL, "the stopping rule reports each design size in df: df is required");
+    if (th.start_n && !th.start) return fail(LAGP_E_INVAL, "start_n without start");
     const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
     hipStream_t s = (hipStream_t)stream;
 
@@ -732,6 +743,24 @@ static int run_predict(const lagp_design* design, const double* XX, int64_t T, c
     rc = build_plan(design, prm, T, n_per ? hn.data() : nullptr, ncand_per ? hm.data() : nullptr, sel != nullptr,
                     status != nullptr, &P);
     if (rc) return rc;
+    if (th.start) {
+        // saved starting designs: sizes in [1, n] per location, read from start_stride columns
+        int32_t smax = prm->n0;
+        if (th.start_n) {
+            std::vector<int32_t> hs(T);
+            hipError_t e = hipMemcpyAsync(hs.data(), th.start_n, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail("start size copy", e);
+            smax = 0;
+            for (int64_t t = 0; t < T; ++t) {
+                const int32_t nt = n_per ? hn[t] : prm->n;
+                if (hs[t] < 1 || hs[t] > nt)
+                    return fail(LAGP_E_INVAL, "location " + std::to_string(t) + ": need 1 <= start size <= n");
+                smax = std::max(smax, hs[t]);
+            }
+        }
+        if (th.start_stride < smax) return fail(LAGP_E_INVAL, "start_stride must be >= the largest start size");
+    }
     rc = check_outputs(o, P.nmax);
     if (rc) return rc;
     if (mle) {
@@ -772,6 +801,22 @@ int lagp_predict(const lagp_design* design, const double* XX, int64_t T, const l
 {
     return run_predict(design, XX, T, prm, ThetaIO{}, nullptr, n_per, ncand_per, mean, s2, df, var, sel, sel_stride,
                        status, stream);
+}
+
+int lagp_predict_ex(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                    const lagp_options* opt, const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2,
+                    int32_t* df, double* var, int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
+{
+    ThetaIO th;
+    if (opt) {
+        th.d_per = opt->d_per;
+        th.start = opt->start;
+        th.start_stride = opt->start_stride;
+        th.start_n = opt->start_n;
+        th.vratio = opt->vratio;
+    }
+    return run_predict(design, XX, T, prm, th, nullptr, n_per, ncand_per, mean, s2, df, var, sel, sel_stride, status,
+                       stream);
 }
 
 int lagp_predict_theta(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,

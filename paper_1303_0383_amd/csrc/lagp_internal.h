@@ -78,6 +78,10 @@ struct DesignLaunch {
     int32_t n0 = 0, n = 0, M = 0;  // uniform values (maxima when per-location arrays are given)
     double theta = 1.0, eta = 0.0;
     const double* theta_per = nullptr;  // nullable: per-location lengthscale (replaces theta)
+    const int32_t* start = nullptr;     // nullable: saved starting designs (replace the n0 nearest)
+    int64_t start_stride = 0;
+    const int32_t* start_n = nullptr;   // nullable: per-location starting-design size (else n0)
+    double vratio = 0.0;                // > 0: variance-ratio stopping threshold
     int32_t precision = 0;
     const int32_t* order = nullptr;   // work item -> location (nullable: identity over T)
     const uint32_t* count = nullptr;  // device-side item count (nullable: T items)

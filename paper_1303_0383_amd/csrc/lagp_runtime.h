@@ -73,11 +73,15 @@ struct Plan {
     size_t total = 0;
 };
 
-// Lengthscale inputs and outputs of the entry points that take them.
+// Optional inputs and outputs of the extended entry points.
 struct ThetaIO {
     const double* d_per = nullptr;  // device T: per-location lengthscale (first design pass)
     double* d1 = nullptr;           // two-stage outputs, device T (nullable)
     double* d2 = nullptr;
+    const int32_t* start = nullptr; // device T x start_stride: saved starting designs
+    int64_t start_stride = 0;
+    const int32_t* start_n = nullptr;   // device T: starting-design sizes (else params->n0)
+    double vratio = 0.0;            // variance-ratio stopping threshold (0: off)
 };
 
 struct Outputs {

@@ -164,13 +164,10 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 __syncthreads();
                 // trailing triangle rows i > m, columns m < k <= i; and u
                 const int tn = n - m - 1;
-                int ii = 0, kk = tid;
-                while (ii < tn && kk > ii) { kk -= ii + 1; ++ii; }
-                for (; ii < tn;) {
+                for (int e = tid; e < tn * (tn + 1) / 2; e += MT) {
+                    const int ii = row_of(e), kk = e - ii * (ii + 1) / 2;
                     const int i = m + 1 + ii, k = m + 1 + kk;
                     Tm[tri(i, k)] -= Tm[tri(i, m)] * Tm[tri(k, m)];
-                    kk += MT;
-                    while (ii < tn && kk > ii) { kk -= ii + 1; ++ii; }
                 }
                 const double um = u[m];
                 for (int i = m + 1 + tid; i < n; i += MT) u[i] -= Tm[tri(i, m)] * um;
@@ -187,11 +184,15 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                     Tm[tri(k, c)] = (c == k) ? 1.0 / lk : Tm[tri(k, c)] / lk;
                 for (int i = k + 1 + tid; i < n; i += MT) col[i] = Tm[tri(i, k)];
                 __syncthreads();
-                const int rows = n - k - 1, w1 = k + 1;
-                for (int e = tid; e < rows * w1; e += MT) {
-                    const int i = k + 1 + e / w1, c = e - (e / w1) * w1;
+                // rows i > k, columns c <= k: (i, c) advances by MT items without dividing per item
+                const int w1 = k + 1, qi = MT / w1, qc = MT - qi * w1;
+                int i = k + 1 + tid / w1, c = tid - (tid / w1) * w1;
+                for (; i < n;) {
                     if (c == k) Tm[tri(i, k)] = -(col[i] * Tm[tri(k, k)]);
                     else Tm[tri(i, c)] -= col[i] * Tm[tri(k, c)];
+                    i += qi;
+                    c += qc;
+                    if (c >= w1) { c -= w1; ++i; }
                 }
                 __syncthreads();
             }
@@ -236,8 +237,9 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             for (int j0 = 0; j0 < n; j0 += PW) {
                 const int pw = (n - j0) < PW ? (n - j0) : PW;
                 // H[a][jj] = sum_{b <= j} dK_ab Li_jb, j = j0 + jj
-                for (int e = tid; e < n * pw; e += MT) {
-                    const int a = e / pw, jj = e - a * pw, j = j0 + jj;
+                for (int e = tid; e < n * PW; e += MT) {
+                    const int a = e / PW, jj = e % PW, j = j0 + jj;
+                    if (jj >= pw) continue;
                     double s = 0.0;
                     for (int b = 0; b <= j; ++b) {
                         const double kd = (a > b) ? Cd[sl(a, b)] : (a < b ? Cd[sl(b, a)] : 0.0);
@@ -247,9 +249,9 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 }
                 __syncthreads();
                 // M_ij = sum_{a <= i} Li_ia H_aj for i >= j
-                for (int e = tid; e < n * pw; e += MT) {
-                    const int i = e / pw, jj = e - i * pw, j = j0 + jj;
-                    if (i < j) continue;
+                for (int e = tid; e < n * PW; e += MT) {
+                    const int i = e / PW, jj = e % PW, j = j0 + jj;
+                    if (jj >= pw || i < j) continue;
                     double s = 0.0;
                     for (int a = 0; a <= i; ++a) s += Tm[tri(i, a)] * H[a * PW + jj];
                     acc[6] += (i == j ? 1.0 : 2.0) * (s * s);
@@ -294,9 +296,9 @@ int threads_for(int nmax)
 {
     if (const char* e = getenv("LAGP_MLE_THREADS")) {
         const int v = atoi(e);
-        if (v == 64 || v == 128 || v == 256) return v;
+        if (v == 64 || v == 128 || v == 256 || v == 512) return v;
     }
-    return nmax <= 24 ? 64 : 128;
+    return nmax <= 24 ? 128 : 256;
 }
 
 }  // namespace
@@ -310,8 +312,9 @@ size_t mle_lds_bytes(int nmax, int p, int threads)
 
 int mle_prepare(int32_t nmax, int p, size_t max_lds, std::string* err)
 {
-    if (mle_lds_bytes(nmax, p, 256) > max_lds) { *err = "local design too large for the likelihood kernel"; return -1; }
-    const void* k[3] = {(const void*)mle_kernel<64>, (const void*)mle_kernel<128>, (const void*)mle_kernel<256>};
+    if (mle_lds_bytes(nmax, p, 512) > max_lds) { *err = "local design too large for the likelihood kernel"; return -1; }
+    const void* k[4] = {(const void*)mle_kernel<64>, (const void*)mle_kernel<128>, (const void*)mle_kernel<256>,
+                        (const void*)mle_kernel<512>};
     for (const void* f : k)
         if (!set_lds_limit(f, max_lds)) { *err = "cannot reserve LDS for the likelihood kernel"; return -2; }
     return 0;
@@ -323,7 +326,10 @@ int mle_run(const MleArgs& a, size_t max_lds, hipStream_t stream, std::string* e
     const int mt = threads_for(a.nmax);
     const size_t lds = mle_lds_bytes(a.nmax, a.p, mt);
     if (lds > max_lds) { *err = "local design too large for the likelihood kernel"; return -1; }
-    int rc = mt == 64 ? launch<64>(a, lds, stream) : mt == 128 ? launch<128>(a, lds, stream) : launch<256>(a, lds, stream);
+    int rc = mt == 64    ? launch<64>(a, lds, stream)
+             : mt == 128 ? launch<128>(a, lds, stream)
+             : mt == 256 ? launch<256>(a, lds, stream)
+                         : launch<512>(a, lds, stream);
     if (rc) { *err = "likelihood kernel launch failed"; return rc; }
     return 0;
 }
