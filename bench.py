@@ -52,6 +52,21 @@ def design_exps(n: int, M: int) -> int:
     return M + sum(M - i - 1 for i in range(n - 1))
 
 
+def mspe_flops(n: int, M: int, p: int, n0: int) -> int:
+    """Algorithmic FP64 flops of the MSPE kernel for one location: gather
+    (3p - 1 per candidate); per step i = 0 .. n-2 and live candidate: four
+    dot products over the candidate's two tile columns (8i), K(s,c) and its
+    theta-derivative (3p + 3), the new tile rows (4), the updates of v, cov,
+    a, b, Q and the W-column dot with z (12), and from step n0-1 on the
+    criterion J (24).  The location-level bordering is O(n^3) in total and
+    left out."""
+    f = M * 3 * p
+    for i in range(n - 1):
+        live = M - i - 1
+        f += live * (8 * i + 3 * p + 19 + (24 if i + 1 >= n0 else 0))
+    return f
+
+
 def workload(name: str, T: int | None):
     import workloads
     if name == "c2_n50":
@@ -79,8 +94,9 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_n50", choices=["c2_n50", "c2", "c1", "c0", "c3", "c4"])
     ap.add_argument("--T", type=int, default=None, help="use only the first T locations")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--method", default="alc", choices=["alc", "alc2"],
-                    help="alc: designs at the fixed lengthscale; alc2: the two-stage scheme with local MLEs")
+    ap.add_argument("--method", default="alc", choices=["alc", "alc2", "mspe"],
+                    help="alc: designs at the fixed lengthscale; alc2: the two-stage scheme with local MLEs; "
+                         "mspe: greedy designs by the MSPE criterion")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="locations in the CPU oracle sample (0: skip)")
     ap.add_argument("--parity-sample", type=int, default=64, help="sampled locations checked against the oracle")
     ap.add_argument("--graph", default="auto", choices=["auto", "on", "off"],
@@ -132,8 +148,11 @@ def main() -> int:
                           status=torch.empty(T, dtype=torch.int8, device=dev))
 
     alc2 = args.method == "alc2"
+    mspe = args.method == "mspe"
+    if mspe and (w.n_per is not None or args.precision != "fp64"):
+        raise SystemExit("--method mspe runs uniform sizes in FP64")
     # graphs capture fixed-shape batches of the one-stage scheme
-    use_graph = not alc2 and (args.graph == "on" or (args.graph == "auto" and w.n_per is not None))
+    use_graph = not (alc2 or mspe) and (args.graph == "on" or (args.graph == "auto" and w.n_per is not None))
     if alc2:
         import workloads
         tmin, tmax = workloads.mle_range(w.X)
@@ -141,7 +160,9 @@ def main() -> int:
         out.theta2 = torch.empty(T, dtype=torch.float64, device=dev)
 
     def eager_step():
-        if alc2:
+        if mspe:
+            D.predict_mspe(XX, w.n0, nmax, Mmax, w.d, w.g, out=out)
+        elif alc2:
             D.predict_alc2(XX, w.n0, nmax, Mmax, w.d, w.g, tmin, tmax, n_per=n_per, ncand_per=M_per,
                            precision=prec, out=out)
         else:
@@ -202,16 +223,18 @@ def main() -> int:
         exps = T * design_exps(w.n, w.ncand)
     passes = 2 if alc2 else 1   # design passes per step
     flops, exps = passes * flops, passes * exps
+    if mspe:
+        flops = T * mspe_flops(w.n, w.ncand, w.p, w.n0)
     launches_per_step = max(1, launches // args.steps)
     per_launch_flops = flops / launches_per_step
     avg_launch_s = des_ms / max(launches, 1) / 1e3
     achieved = per_launch_flops / avg_launch_s / 1e12
-    roofline = {"kernel": "design_kernel", "bound": "alu", "achieved": round(achieved, 3),
+    roofline = {"kernel": "mspe_kernel" if mspe else "design_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": launches_per_step,
                 "flops_per_launch": per_launch_flops, "exps_per_launch": exps / launches_per_step,
                 "exp_rate_G_per_s": round(exps / launches_per_step / avg_launch_s / 1e9, 2)}
-    traffic_file = os.path.join(ROOT, "profiles", f"design_kernel_{args.workload}_traffic.txt")
+    traffic_file = os.path.join(ROOT, "profiles", f"{roofline['kernel']}_{args.workload}_traffic.txt")
     if os.path.exists(traffic_file) and args.precision == "fp64":
         for line in open(traffic_file):
             if line.startswith("bytes_per_launch:"):
@@ -256,6 +279,20 @@ def main() -> int:
         except AssertionError as e:
             m = {"ok": False, "error": str(e)}
         result["parity"] = {"locations": len(idx), "kind": "mixed", **m}
+    elif args.parity_sample > 0 and mspe:
+        # sequences against the oracle's greedy MSPE search; predictions where they agree
+        import oracle
+        idx = np.sort(rng.choice(T, min(args.parity_sample, T), replace=False))
+        same = 0
+        worst = 0.0
+        for t in idx:
+            rc, so, o, _ = oracle.mspe_local(w.X, w.y, w.XX[t], w.n0, w.n, w.ncand, w.d, w.g)
+            if np.array_equal(so, res["sel"][t, :w.n]):
+                same += 1
+                worst = max(worst, abs(res["mean"][t] - o[0]) / max(abs(o[0]), float(np.std(w.y))),
+                            abs(res["s2"][t] - o[1]) / o[1])
+        result["parity"] = {"locations": len(idx), "kind": "mspe", "identical": same,
+                            "worst_rel": float(f"{worst:.3e}"), "ok": bool(same == len(idx) and worst <= 1e-9)}
     elif args.parity_sample > 0 and alc2:
         # Stage by stage on a sample, each stage fed the GPU's previous one:
         # the second designs against the oracle's at the GPU's theta1, theta2
@@ -311,7 +348,12 @@ def main() -> int:
         idx = np.sort(rng.choice(T, min(args.cpu_sample, T), replace=False))
         sub = w.subset(idx)
         tc = time.perf_counter()
-        if alc2:
+        if mspe:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(lambda t: oracle.mspe_local(sub.X, sub.y, sub.XX[t], sub.n0, sub.n, sub.ncand, sub.d,
+                                                        sub.g), range(len(idx))))
+        elif alc2:
             # the oracle's two-stage function is per location: a thread pool over
             # the sample (the ctypes calls release the interpreter lock)
             from concurrent.futures import ThreadPoolExecutor

@@ -60,6 +60,7 @@ _lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P,
                               C.c_int64, _P, _P]
 _lib.lagp_predict_ex.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_options), _P, _P, _P, _P,
                                 _P, _P, _P, C.c_int64, _P, _P]
+_lib.lagp_predict_mspe.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, C.c_int64, _P, _P]
 _lib.lagp_predict_theta.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P, _P,
                                    C.c_int64, _P, _P]
 _lib.lagp_predict_alc2.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_mle_params), _P, _P, _P,
@@ -91,7 +92,7 @@ for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_byt
            "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
            "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant",
            "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats", "lagp_predict_theta",
-           "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex"):
+           "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex", "lagp_predict_mspe"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -177,6 +178,12 @@ def lagp_predict_ex(design, XX, T: int, params: lagp_params, opts, n_per, ncand_
     _check(_lib.lagp_predict_ex(design, _ptr(XX), T, C.byref(params), None if opts is None else C.byref(opts),
                                 _ptr(n_per), _ptr(ncand_per), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var), _ptr(sel),
                                 sel_stride, _ptr(status), _stream(stream)))
+
+
+def lagp_predict_mspe(design, XX, T: int, params: lagp_params, mean, s2, df, var, sel, sel_stride: int, status,
+                      stream=None) -> None:
+    _check(_lib.lagp_predict_mspe(design, _ptr(XX), T, C.byref(params), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var),
+                                  _ptr(sel), sel_stride, _ptr(status), _stream(stream)))
 
 
 def lagp_predict_theta(design, XX, T: int, params: lagp_params, d_per, n_per, ncand_per, mean, s2, df, var, sel,
@@ -365,6 +372,18 @@ class Design:
         out.sel = sel
         lagp_predict_designs(self._h, XX, T, sel, n, n_per, n, d, d_per, g, out.mean, out.s2, out.df, out.var,
                              out.status, stream)
+        return out
+
+    def predict_mspe(self, XX, n0: int, n: int, ncand: int, d: float, g: float, strict: bool = False,
+                     out: Optional[Prediction] = None, stream=None) -> Prediction:
+        """Greedy MSPE designs (eq mspe) and prediction."""
+        XX = XX.contiguous()
+        T = XX.shape[0]
+        if out is None:
+            out = _outputs(T, n, XX.device)
+        prm = lagp_params(n0, n, ncand, d, g, LAGP_PREC_FP64, LAGP_STRICT if strict else 0)
+        lagp_predict_mspe(self._h, XX, T, prm, out.mean, out.s2, out.df, out.var, out.sel, out.sel.shape[1],
+                          out.status, stream)
         return out
 
     def mle(self, sel, d0, g: float, tmin: float, tmax: float, n_per=None, maxit: int = MLE_MAXIT,

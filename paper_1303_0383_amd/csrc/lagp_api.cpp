@@ -844,6 +844,110 @@ int lagp_predict_alc2(const lagp_design* design, const double* XX, int64_t T, co
                        stream);
 }
 
+int lagp_predict_mspe(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm, double* mean,
+                      double* s2, int32_t* df, double* var, int32_t* sel, int64_t sel_stride, int8_t* status,
+                      void* stream)
+{
+    if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
+    if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
+    const int64_t N = design->dev.N;
+    if (!(prm->d > 0.0) || !isfinite(prm->d)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
+    if (!(prm->g >= 0.0) || !isfinite(prm->g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
+    if (prm->precision != LAGP_PREC_FP64) return fail(LAGP_E_INVAL, "the MSPE criterion runs in FP64 only");
+    if (prm->flags & ~(uint32_t)LAGP_STRICT) return fail(LAGP_E_INVAL, "unknown flag");
+    if (prm->n0 < 3) return fail(LAGP_E_INVAL, "the MSPE criterion needs n0 >= 3 (it scales by j - 2)");
+    if (prm->n < prm->n0) return fail(LAGP_E_INVAL, "n must be >= n0");
+    if (prm->ncand < prm->n || prm->ncand > N) return fail(LAGP_E_INVAL, "need n <= ncand <= N");
+    if (prm->ncand > 2048) return fail(LAGP_E_INVAL, "the MSPE kernel takes at most 2048 candidates");
+    if (lagp::mspe_lds_bytes(prm->n, design->dev.p) > design->max_lds)
+        return fail(LAGP_E_INVAL, "n too large for the MSPE kernel");
+    if (T == 0) return LAGP_OK;
+    if (!XX || !mean || !s2) return fail(LAGP_E_INVAL, "XX, mean and s2 are required");
+    int rc = check_device(design);
+    if (rc) return rc;
+    if (!is_device_ptr(XX)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
+    const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
+    rc = check_outputs(o, prm->n);
+    if (rc) return rc;
+    lagp_design* d = const_cast<lagp_design*>(design);
+    hipStream_t s = (hipStream_t)stream;
+    const int p = d->dev.p;
+    const int M = prm->ncand;
+    const int64_t tc_max = std::min(kChunk, T);
+    const int blocks = (int)std::min<int64_t>(tc_max, d->num_cu);
+    const size_t knn_b = lagp::align256(lagp::knn_workspace_bytes(tc_max, lagp::KNN_BUCKET_MAX));
+    const size_t cand_b = lagp::align256((size_t)tc_max * M * sizeof(int32_t));
+    const size_t slab = lagp::align256(lagp::mspe_slab_bytes(prm->n, M, p));
+    const size_t total = knn_b + cand_b + 256 + (size_t)blocks * slab;
+    rc = ensure_ws(d, total, s);
+    if (rc) return rc;
+    std::string err;
+    if (lagp::knn_prepare(p, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    int r = lagp::mspe_prepare(prm->n, M, p, d->max_lds, &err);
+    if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    char* q = (char*)d->ws;
+    void* knn_ws = q;
+    int32_t* cand = (int32_t*)(q + knn_b);
+    unsigned int* counter = (unsigned int*)(q + knn_b + cand_b);
+    double* scratch = (double*)(q + knn_b + cand_b + 256);
+    auto mark = [&](int phase) {
+        if (!d->timing) return;
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        d->ev.push_back(e);
+        d->ev_phase.push_back(phase);
+        d->ev_launches.push_back(phase == LAGP_PHASE_DESIGN ? 1 : 0);
+        (void)hipEventRecord(e, s);
+    };
+    for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
+        const int64_t tc = std::min(kChunk, T - t0);
+        const double* xx = XX + t0 * p;
+        mark(-1);
+        r = lagp::knn_run(d->dev, xx, tc, M, nullptr, cand, M, false, knn_ws, knn_b, s, d->num_cu, d->max_lds, &err);
+        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        mark(LAGP_PHASE_KNN);
+        lagp::MspeArgs a;
+        a.Xaos = d->dev.Xaos;
+        a.y = d->dev.y;
+        a.p = p;
+        a.XX = xx;
+        a.T = tc;
+        a.cand = cand;
+        a.cand_stride = M;
+        a.n0 = prm->n0;
+        a.n = prm->n;
+        a.M = M;
+        a.nmax = prm->n;
+        a.theta = prm->d;
+        a.eta = prm->g;
+        a.mean = mean + t0;
+        a.s2 = s2 + t0;
+        a.df = df ? df + t0 : nullptr;
+        a.var = var ? var + t0 : nullptr;
+        a.sel = sel ? sel + t0 * sel_stride : nullptr;
+        a.sel_stride = sel_stride;
+        a.status = status ? status + t0 : nullptr;
+        a.scratch = scratch;
+        a.scratch_stride = (int64_t)(slab / sizeof(double));
+        a.counter = counter;
+        r = lagp::mspe_run(a, (int)std::min<int64_t>(tc, blocks), d->max_lds, s, &err);
+        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        mark(LAGP_PHASE_DESIGN);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail("launch", e);
+    if (prm->flags & LAGP_STRICT) {
+        if (!status) return fail(LAGP_E_INVAL, "strict mode needs the status output");
+        std::vector<int8_t> hs(T);
+        e = hipMemcpyAsync(hs.data(), status, T, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail("status copy", e);
+        for (int8_t v : hs)
+            if (v != LAGP_LOC_OK) return fail(LAGP_E_NOTPD, "some location's local covariance was not positive definite");
+    }
+    return LAGP_OK;
+}
+
 int lagp_mle(const lagp_design* design, int64_t T, const int32_t* sel, int64_t sel_stride, const int32_t* n_per,
              int32_t n, const double* d0_per, double d0, double g, const lagp_mle_params* mle, double* d_hat,
              int32_t* iters, int8_t* status, void* stream)

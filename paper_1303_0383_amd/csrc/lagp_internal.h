@@ -159,6 +159,33 @@ struct MleArgs {
     int8_t* status = nullptr;       // nullable: 0 OK, 1 failed
 };
 size_t mle_lds_bytes(int nmax, int p, int threads);
+
+// ---- greedy MSPE local designs (mspe.hip)
+struct MspeArgs {
+    const double* Xaos = nullptr;
+    const double* y = nullptr;
+    int p = 0;
+    const double* XX = nullptr;     // T x p
+    int64_t T = 0;
+    const int32_t* cand = nullptr;  // T x cand_stride candidate sets
+    int64_t cand_stride = 0;
+    int n0 = 0, n = 0, M = 0, nmax = 0;
+    double theta = 1.0, eta = 0.0;
+    double* mean = nullptr;
+    double* s2 = nullptr;
+    int32_t* df = nullptr;
+    double* var = nullptr;
+    int32_t* sel = nullptr;
+    int64_t sel_stride = 0;
+    int8_t* status = nullptr;
+    double* scratch = nullptr;      // blocks x scratch_stride doubles
+    int64_t scratch_stride = 0;
+    unsigned int* counter = nullptr;
+};
+size_t mspe_lds_bytes(int nmax, int p);
+size_t mspe_slab_bytes(int nmax, int Mmax, int p);
+int mspe_prepare(int32_t nmax, int32_t Mmax, int p, size_t max_lds, std::string* err);
+int mspe_run(const MspeArgs& a, int blocks, size_t max_lds, hipStream_t stream, std::string* err);
 int mle_prepare(int32_t nmax, int p, size_t max_lds, std::string* err);
 int mle_run(const MleArgs& a, size_t max_lds, hipStream_t stream, std::string* err);
 
