@@ -18,16 +18,18 @@
 //   * builds K (packed lower triangle) and dK (packed strictly-lower
 //     triangle) from the design coordinates held in LDS;
 //   * factorises K right-looking in place, carrying u = L^{-1} Y, and keeps
-//     the pivots L_kk;
-//   * overwrites L with L^{-1} in place by Gauss-Jordan elimination of one
-//     column per pair of barriers (the column about to be eliminated is
-//     copied aside first);
+//     the pivots L_kk -- one barrier per column, each column scaled during
+//     the next column's phase;
+//   * overwrites L with L^{-1} in place by Gauss-Jordan elimination, one
+//     barrier per column (each row scaled during the next phase, the next
+//     column of L copied aside first);
 //   * forms w = K^{-1} Y = L^{-T} u and k = dK w, and from them
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
 //     K^{-1} = L^{-T} L^{-1} computed as they are used, and
 //     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of PW columns of
-//     H = dK L^{-T} at a time;
+//     H = dK L^{-T} at a time (one panel formed while the previous one is
+//     used);
 //   * takes the safeguarded Newton step on l'(theta) = 0.
 // The step rule: where l'' < 0 the step is -l'/l''; elsewhere it is theta in
 // the direction of l'; a step leaving (tmin, tmax) goes half way to the
@@ -53,12 +55,16 @@ constexpr int NRED = 7; // sums reduced per iterate
 __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }   // lower, diagonal included
 __device__ __forceinline__ int sl(int i, int k) { return i * (i - 1) / 2 + k; }    // strictly lower, i > k
 
-// Row of packed-lower index e (a(a+1)/2 <= e < (a+1)(a+2)/2).
+// Row of packed-lower index e (a(a+1)/2 <= e < (a+1)(a+2)/2).  The float
+// estimate is within one of the row for every index a design of up to a few
+// hundred points has, so one branch-free correction each way suffices (a
+// loop here compiles to far more instructions than the multiply-add it
+// feeds).
 __device__ __forceinline__ int row_of(int e)
 {
     int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-    while (a > 0 && a * (a + 1) / 2 > e) --a;
-    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    a -= (a * (a + 1) / 2 > e) ? 1 : 0;
+    a += ((a + 1) * (a + 2) / 2 <= e) ? 1 : 0;
     return a;
 }
 
@@ -105,13 +111,14 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
     double* xs = sm;                              // [nmax][p] design coordinates
     double* Tm = xs + (size_t)nm * p;             // packed lower: K -> L -> L^{-1}
     double* Cd = Tm + (size_t)nm * (nm + 1) / 2;  // packed strictly lower: dK
-    double* H = Cd + (size_t)nm * (nm - 1) / 2;   // [nmax][PW] panel of dK L^{-T}
-    double* yv = H + (size_t)nm * PW;             // Y
+    double* Hb = Cd + (size_t)nm * (nm - 1) / 2;  // [2][nmax][PW] panels of dK L^{-T}
+    double* yv = Hb + 2 * (size_t)nm * PW;        // Y
     double* u = yv + nm;                          // L^{-1} Y
     double* w = u + nm;                           // K^{-1} Y
     double* kw = w + nm;                          // dK K^{-1} Y
-    double* col = kw + nm;                        // column being eliminated
-    double* piv = col + nm;                       // pivots L_kk
+    double* col = kw + nm;                        // columns of L being eliminated (two buffers)
+    double* col2 = col + nm;
+    double* piv = col2 + nm;                      // pivots L_kk
     double* red = piv + nm;                       // [NRED][MT/64]
     __shared__ int bad, done;
     __shared__ double sh_theta;
@@ -148,54 +155,71 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             }
             for (int a = tid; a < n; a += MT) u[a] = yv[a];
             __syncthreads();
-            // ---- Cholesky, right-looking, with u = L^{-1} Y
+            // ---- Cholesky, right-looking, one barrier per column: the pivot
+            //      column m is used unscaled (products divided by the pivot) and
+            //      scaled in place during column m+1's phase, when nothing reads
+            //      it; u = L^{-1} Y is carried the same way.
             int fail = 0;
             for (int m = 0; m < n; ++m) {
                 const double pm = Tm[tri(m, m)];
                 if (!(pm > 0.0)) { fail = 1; break; }   // uniform: every thread read the same pivot
-                const double dm = sqrt(pm);
-                __syncthreads();   // the pivot has been read everywhere before it is overwritten
-                if (tid == 0) {
-                    Tm[tri(m, m)] = dm;
-                    piv[m] = dm;
-                    u[m] = u[m] / dm;
+                const double rpm = 1.0 / pm;
+                if (m > 0) {
+                    const double dp = piv[m - 1];
+                    for (int i = m + tid; i < n; i += MT) Tm[tri(i, m - 1)] = Tm[tri(i, m - 1)] / dp;
+                    if (tid == 0) u[m - 1] = u[m - 1] / dp;
                 }
-                for (int i = m + 1 + tid; i < n; i += MT) Tm[tri(i, m)] = Tm[tri(i, m)] / dm;
-                __syncthreads();
+                if (tid == 0) piv[m] = sqrt(pm);
                 // trailing triangle rows i > m, columns m < k <= i; and u
                 const int tn = n - m - 1;
                 for (int e = tid; e < tn * (tn + 1) / 2; e += MT) {
                     const int ii = row_of(e), kk = e - ii * (ii + 1) / 2;
                     const int i = m + 1 + ii, k = m + 1 + kk;
-                    Tm[tri(i, k)] -= Tm[tri(i, m)] * Tm[tri(k, m)];
+                    Tm[tri(i, k)] -= (Tm[tri(i, m)] * Tm[tri(k, m)]) * rpm;
                 }
                 const double um = u[m];
-                for (int i = m + 1 + tid; i < n; i += MT) u[i] -= Tm[tri(i, m)] * um;
+                for (int i = m + 1 + tid; i < n; i += MT) u[i] -= (Tm[tri(i, m)] * um) * rpm;
                 __syncthreads();
             }
             if (fail) {
                 if (tid == 0) bad = 1;
                 break;
             }
-            // ---- L^{-1} in place: Gauss-Jordan on the columns of L
+            if (tid == 0) u[n - 1] = u[n - 1] / piv[n - 1];   // column n-1 has no entries below its pivot
+            // ---- L^{-1} in place, one barrier per column: row k of X = L^{-1} is
+            //      used unscaled (times 1/L_kk on the fly) and scaled during the
+            //      next phase; column k+1 of L is copied aside in phase k (two
+            //      buffers), before phase k+1 overwrites it.
+            for (int i = 1 + tid; i < n; i += MT) col[i] = Tm[tri(i, 0)];
+            __syncthreads();
             for (int k = 0; k < n; ++k) {
-                const double lk = piv[k];
-                for (int c = tid; c <= k; c += MT)
-                    Tm[tri(k, c)] = (c == k) ? 1.0 / lk : Tm[tri(k, c)] / lk;
-                for (int i = k + 1 + tid; i < n; i += MT) col[i] = Tm[tri(i, k)];
-                __syncthreads();
+                const double rk = 1.0 / piv[k];
+                const double* ck = (k & 1) ? col2 : col;
+                double* cn = (k & 1) ? col : col2;
+                if (k > 0) {
+                    const double rp = 1.0 / piv[k - 1];
+                    for (int c = tid; c < k - 1; c += MT) Tm[tri(k - 1, c)] = Tm[tri(k - 1, c)] * rp;
+                    if (tid == 0) Tm[tri(k - 1, k - 1)] = rp;
+                }
+                for (int i = k + 2 + tid; i < n; i += MT) cn[i] = Tm[tri(i, k + 1)];
                 // rows i > k, columns c <= k: (i, c) advances by MT items without dividing per item
                 const int w1 = k + 1, qi = MT / w1, qc = MT - qi * w1;
                 int i = k + 1 + tid / w1, c = tid - (tid / w1) * w1;
                 for (; i < n;) {
-                    if (c == k) Tm[tri(i, k)] = -(col[i] * Tm[tri(k, k)]);
-                    else Tm[tri(i, c)] -= col[i] * Tm[tri(k, c)];
+                    if (c == k) Tm[tri(i, k)] = -(ck[i] * rk);
+                    else Tm[tri(i, c)] -= ck[i] * (Tm[tri(k, c)] * rk);
                     i += qi;
                     c += qc;
                     if (c >= w1) { c -= w1; ++i; }
                 }
                 __syncthreads();
             }
+            {
+                const double rp = 1.0 / piv[n - 1];
+                for (int c = tid; c < n - 1; c += MT) Tm[tri(n - 1, c)] = Tm[tri(n - 1, c)] * rp;
+                if (tid == 0) Tm[tri(n - 1, n - 1)] = rp;
+            }
+            __syncthreads();
             // ---- w = L^{-T} u, then k = dK w
             for (int b = tid; b < n; b += MT) {
                 double s = 0.0;
@@ -233,28 +257,37 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 acc[4] += 2.0 * ki * kd;
                 acc[5] += 2.0 * ki * kdd;
             }
-            // ---- tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2, PW columns at a time
-            for (int j0 = 0; j0 < n; j0 += PW) {
-                const int pw = (n - j0) < PW ? (n - j0) : PW;
-                // H[a][jj] = sum_{b <= j} dK_ab Li_jb, j = j0 + jj
-                for (int e = tid; e < n * PW; e += MT) {
-                    const int a = e / PW, jj = e % PW, j = j0 + jj;
-                    if (jj >= pw) continue;
-                    double s = 0.0;
-                    for (int b = 0; b <= j; ++b) {
-                        const double kd = (a > b) ? Cd[sl(a, b)] : (a < b ? Cd[sl(b, a)] : 0.0);
-                        s += kd * Tm[tri(j, b)];
+            // ---- tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2, PW columns at a time:
+            //      phase ph forms panel ph of H = dK L^{-T} and, from the other
+            //      buffer, the entries M_ij (i >= j) of panel ph - 1
+            const int np = (n + PW - 1) / PW;
+            for (int ph = 0; ph <= np; ++ph) {
+                if (ph < np) {
+                    const int j0 = ph * PW, pw = (n - j0) < PW ? (n - j0) : PW;
+                    double* H = Hb + (size_t)(ph & 1) * nm * PW;
+                    // H[a][jj] = sum_{b <= j} dK_ab Li_jb, j = j0 + jj
+                    for (int e = tid; e < n * PW; e += MT) {
+                        const int a = e / PW, jj = e % PW, j = j0 + jj;
+                        if (jj >= pw) continue;
+                        double s = 0.0;
+                        for (int b = 0; b <= j; ++b) {
+                            const double kd = (a > b) ? Cd[sl(a, b)] : (a < b ? Cd[sl(b, a)] : 0.0);
+                            s += kd * Tm[tri(j, b)];
+                        }
+                        H[a * PW + jj] = s;
                     }
-                    H[a * PW + jj] = s;
                 }
-                __syncthreads();
-                // M_ij = sum_{a <= i} Li_ia H_aj for i >= j
-                for (int e = tid; e < n * PW; e += MT) {
-                    const int i = e / PW, jj = e % PW, j = j0 + jj;
-                    if (jj >= pw || i < j) continue;
-                    double s = 0.0;
-                    for (int a = 0; a <= i; ++a) s += Tm[tri(i, a)] * H[a * PW + jj];
-                    acc[6] += (i == j ? 1.0 : 2.0) * (s * s);
+                if (ph > 0) {
+                    const int j0 = (ph - 1) * PW, pw = (n - j0) < PW ? (n - j0) : PW;
+                    const double* H = Hb + (size_t)((ph - 1) & 1) * nm * PW;
+                    // M_ij = sum_{a <= i} Li_ia H_aj for i >= j
+                    for (int e = tid; e < n * PW; e += MT) {
+                        const int i = e / PW, jj = e % PW, j = j0 + jj;
+                        if (jj >= pw || i < j) continue;
+                        double s = 0.0;
+                        for (int a = 0; a <= i; ++a) s += Tm[tri(i, a)] * H[a * PW + jj];
+                        acc[6] += (i == j ? 1.0 : 2.0) * (s * s);
+                    }
                 }
                 __syncthreads();
             }
@@ -306,7 +339,7 @@ int threads_for(int nmax)
 size_t mle_lds_bytes(int nmax, int p, int threads)
 {
     const size_t nm = (size_t)nmax;
-    return (nm * p + nm * (nm + 1) / 2 + nm * (nm - 1) / 2 + nm * PW + 6 * nm + (size_t)NRED * (threads / 64)) *
+    return (nm * p + nm * (nm + 1) / 2 + nm * (nm - 1) / 2 + 2 * nm * PW + 7 * nm + (size_t)NRED * (threads / 64)) *
            sizeof(double);
 }
 
