@@ -302,3 +302,26 @@ def test_alc2_invalid_arguments(c0, lagp):
         D.predict_alc2(XX, 1, 1, 10, w.d, w.g, 0.1, 1.0)          # n < 2
     with pytest.raises(E):
         D.predict_alc2(XX, w.n0, w.n, w.ncand, w.d, w.g, 1.0, 0.1)  # tmin >= tmax
+
+
+def test_alc2_failure_stays_local(lagp):
+    """A location whose first design cannot be factorised (duplicated points,
+    no nugget) ends with status NOTPD and NaN estimates and outputs; the
+    other locations are unaffected."""
+    import torch
+    r = np.random.default_rng(21)
+    X = r.uniform(0, 1, (400, 2))
+    X[1] = X[0]                      # an exact duplicate next to the first location
+    y = np.sin(4 * X[:, 0]) + X[:, 1]
+    XX = np.vstack([X[0] + 1e-4, r.uniform(0.2, 0.8, (5, 2))])
+    D = lagp.Design(X, y)
+    out = D.predict_alc2(_dev(XX), 3, 12, 60, 0.3, 0.0, 1e-3, 2.0)
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    assert st[0] == lagp.LAGP_LOC_NOTPD
+    assert np.isnan(out.mean[0].item()) and np.isnan(out.theta1[0].item()) and np.isnan(out.theta2[0].item())
+    ok = D.predict_alc2(_dev(XX[1:]), 3, 12, 60, 0.3, 0.0, 1e-3, 2.0)
+    torch.cuda.synchronize()
+    assert np.all(st[1:] == 0)
+    assert torch.equal(out.mean[1:], ok.mean) and torch.equal(out.theta2[1:], ok.theta2)
+    D.close()
