@@ -453,7 +453,8 @@ def serve_bench(args, lagp, torch) -> int:
     lagp.lagp_phase_times(D.handle)
     D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd)
     torch.cuda.synchronize()
-    knn_ms, des_ms, launches = lagp.lagp_phase_times(D.handle)
+    phase, launches = lagp.lagp_phase_times(D.handle)
+    knn_ms, des_ms = phase["knn"], phase["design"]
     lagp.lagp_timing_enable(D.handle, False)
     flops = sum(design_flops(int(a), int(b), 4, prm["n0"]) for a, b in zip(n_per, M_per))
     achieved = flops / (des_ms / 1e3) / 1e12
