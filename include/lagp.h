@@ -182,12 +182,12 @@ int lagp_predict_designs(const lagp_design *design, const double *XX, int64_t T,
  * expected Fisher information G of eq G (F_j = -l''(theta), eq d2l, plus the
  * candidate's expected information); the next point minimises J (ties to the
  * smaller design index).  The derivative of V_j(c) is that of psi v_j(c)/(j-2)
- * (dpsi/dtheta = -Y'K^{-1} dK K^{-1}Y).  Outputs as in lagp_predict.  FP64
- * only; uniform sizes with 3 <= n0 <= n <= ncand <= min(N, 2048); n is limited
- * by LDS (about 96 at p = 8). */
+ * (dpsi/dtheta = -Y'K^{-1} dK K^{-1}Y).  Sizes and outputs as in lagp_predict
+ * (n_per, ncand_per optional device arrays).  FP64 only; 3 <= n0 <= n <= ncand
+ * <= min(N, 2048); n is limited by LDS (about 96 at p = 8). */
 int lagp_predict_mspe(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
-                      double *mean, double *s2, int32_t *df, double *var, int32_t *sel, int64_t sel_stride,
-                      int8_t *status, void *stream);
+                      const int32_t *n_per, const int32_t *ncand_per, double *mean, double *s2, int32_t *df,
+                      double *var, int32_t *sel, int64_t sel_stride, int8_t *status, void *stream);
 
 /* ---- Local inference of the lengthscale (Sections 3.2 and 4.2).
  *

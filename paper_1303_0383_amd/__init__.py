@@ -60,7 +60,8 @@ _lib.lagp_predict.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P,
                               C.c_int64, _P, _P]
 _lib.lagp_predict_ex.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_options), _P, _P, _P, _P,
                                 _P, _P, _P, C.c_int64, _P, _P]
-_lib.lagp_predict_mspe.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, C.c_int64, _P, _P]
+_lib.lagp_predict_mspe.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P, C.c_int64,
+                                  _P, _P]
 _lib.lagp_predict_theta.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, _P, _P, _P,
                                    C.c_int64, _P, _P]
 _lib.lagp_predict_alc2.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), C.POINTER(lagp_mle_params), _P, _P, _P,
@@ -180,10 +181,11 @@ def lagp_predict_ex(design, XX, T: int, params: lagp_params, opts, n_per, ncand_
                                 sel_stride, _ptr(status), _stream(stream)))
 
 
-def lagp_predict_mspe(design, XX, T: int, params: lagp_params, mean, s2, df, var, sel, sel_stride: int, status,
-                      stream=None) -> None:
-    _check(_lib.lagp_predict_mspe(design, _ptr(XX), T, C.byref(params), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var),
-                                  _ptr(sel), sel_stride, _ptr(status), _stream(stream)))
+def lagp_predict_mspe(design, XX, T: int, params: lagp_params, n_per, ncand_per, mean, s2, df, var, sel,
+                      sel_stride: int, status, stream=None) -> None:
+    _check(_lib.lagp_predict_mspe(design, _ptr(XX), T, C.byref(params), _ptr(n_per), _ptr(ncand_per), _ptr(mean),
+                                  _ptr(s2), _ptr(df), _ptr(var), _ptr(sel), sel_stride, _ptr(status),
+                                  _stream(stream)))
 
 
 def lagp_predict_theta(design, XX, T: int, params: lagp_params, d_per, n_per, ncand_per, mean, s2, df, var, sel,
@@ -374,16 +376,17 @@ class Design:
                              out.status, stream)
         return out
 
-    def predict_mspe(self, XX, n0: int, n: int, ncand: int, d: float, g: float, strict: bool = False,
-                     out: Optional[Prediction] = None, stream=None) -> Prediction:
+    def predict_mspe(self, XX, n0: int, n: int, ncand: int, d: float, g: float, n_per=None, ncand_per=None,
+                     strict: bool = False, out: Optional[Prediction] = None, stream=None) -> Prediction:
         """Greedy MSPE designs (eq mspe) and prediction."""
         XX = XX.contiguous()
         T = XX.shape[0]
+        nmax = int(n_per.max().item()) if (n_per is not None and T) else n
         if out is None:
-            out = _outputs(T, n, XX.device)
+            out = _outputs(T, nmax, XX.device)
         prm = lagp_params(n0, n, ncand, d, g, LAGP_PREC_FP64, LAGP_STRICT if strict else 0)
-        lagp_predict_mspe(self._h, XX, T, prm, out.mean, out.s2, out.df, out.var, out.sel, out.sel.shape[1],
-                          out.status, stream)
+        lagp_predict_mspe(self._h, XX, T, prm, n_per, ncand_per, out.mean, out.s2, out.df, out.var, out.sel,
+                          out.sel.shape[1], out.status, stream)
         return out
 
     def mle(self, sel, d0, g: float, tmin: float, tmax: float, n_per=None, maxit: int = MLE_MAXIT,

@@ -844,9 +844,9 @@ int lagp_predict_alc2(const lagp_design* design, const double* XX, int64_t T, co
                        stream);
 }
 
-int lagp_predict_mspe(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm, double* mean,
-                      double* s2, int32_t* df, double* var, int32_t* sel, int64_t sel_stride, int8_t* status,
-                      void* stream)
+int lagp_predict_mspe(const lagp_design* design, const double* XX, int64_t T, const lagp_params* prm,
+                      const int32_t* n_per, const int32_t* ncand_per, double* mean, double* s2, int32_t* df,
+                      double* var, int32_t* sel, int64_t sel_stride, int8_t* status, void* stream)
 {
     if (!design || !prm) return fail(LAGP_E_INVAL, "design or params is NULL");
     if (T < 0) return fail(LAGP_E_INVAL, "T < 0");
@@ -856,34 +856,52 @@ int lagp_predict_mspe(const lagp_design* design, const double* XX, int64_t T, co
     if (prm->precision != LAGP_PREC_FP64) return fail(LAGP_E_INVAL, "the MSPE criterion runs in FP64 only");
     if (prm->flags & ~(uint32_t)LAGP_STRICT) return fail(LAGP_E_INVAL, "unknown flag");
     if (prm->n0 < 3) return fail(LAGP_E_INVAL, "the MSPE criterion needs n0 >= 3 (it scales by j - 2)");
-    if (prm->n < prm->n0) return fail(LAGP_E_INVAL, "n must be >= n0");
-    if (prm->ncand < prm->n || prm->ncand > N) return fail(LAGP_E_INVAL, "need n <= ncand <= N");
-    if (prm->ncand > 2048) return fail(LAGP_E_INVAL, "the MSPE kernel takes at most 2048 candidates");
-    if (lagp::mspe_lds_bytes(prm->n, design->dev.p) > design->max_lds)
-        return fail(LAGP_E_INVAL, "n too large for the MSPE kernel");
     if (T == 0) return LAGP_OK;
     if (!XX || !mean || !s2) return fail(LAGP_E_INVAL, "XX, mean and s2 are required");
     int rc = check_device(design);
     if (rc) return rc;
-    if (!is_device_ptr(XX)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
-    const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
-    rc = check_outputs(o, prm->n);
-    if (rc) return rc;
+    const void* devptrs[] = {XX, n_per, ncand_per};
+    for (const void* q : devptrs)
+        if (q && !is_device_ptr(q)) return fail(LAGP_E_INVAL, "array arguments must be device pointers");
     lagp_design* d = const_cast<lagp_design*>(design);
     hipStream_t s = (hipStream_t)stream;
+    // per-location sizes come to the host for checking
+    std::vector<int32_t> hn(n_per ? T : 0), hm(ncand_per ? T : 0);
+    if (n_per || ncand_per) {
+        hipError_t e = hipSuccess;
+        if (n_per) e = hipMemcpyAsync(hn.data(), n_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && ncand_per)
+            e = hipMemcpyAsync(hm.data(), ncand_per, T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail("per-location size copy", e);
+    }
+    int32_t nmax = 0, Mmax = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t nt = n_per ? hn[t] : prm->n, mt = ncand_per ? hm[t] : prm->ncand;
+        if (nt < prm->n0 || mt < nt || mt > N)
+            return fail(LAGP_E_INVAL, "location " + std::to_string(t) + ": need n0 <= n <= ncand <= N");
+        nmax = std::max(nmax, nt);
+        Mmax = std::max(Mmax, mt);
+        if (!n_per && !ncand_per) break;
+    }
+    if (Mmax > 2048) return fail(LAGP_E_INVAL, "the MSPE kernel takes at most 2048 candidates");
+    if (lagp::mspe_lds_bytes(nmax, design->dev.p) > design->max_lds)
+        return fail(LAGP_E_INVAL, "n too large for the MSPE kernel");
+    const Outputs o = {mean, s2, df, var, sel, sel_stride, status};
+    rc = check_outputs(o, nmax);
+    if (rc) return rc;
     const int p = d->dev.p;
-    const int M = prm->ncand;
     const int64_t tc_max = std::min(kChunk, T);
     const int blocks = (int)std::min<int64_t>(tc_max, d->num_cu);
     const size_t knn_b = lagp::align256(lagp::knn_workspace_bytes(tc_max, lagp::KNN_BUCKET_MAX));
-    const size_t cand_b = lagp::align256((size_t)tc_max * M * sizeof(int32_t));
-    const size_t slab = lagp::align256(lagp::mspe_slab_bytes(prm->n, M, p));
+    const size_t cand_b = lagp::align256((size_t)tc_max * Mmax * sizeof(int32_t));
+    const size_t slab = lagp::align256(lagp::mspe_slab_bytes(nmax, Mmax, p));
     const size_t total = knn_b + cand_b + 256 + (size_t)blocks * slab;
     rc = ensure_ws(d, total, s);
     if (rc) return rc;
     std::string err;
     if (lagp::knn_prepare(p, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
-    int r = lagp::mspe_prepare(prm->n, M, p, d->max_lds, &err);
+    int r = lagp::mspe_prepare(nmax, Mmax, p, d->max_lds, &err);
     if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     char* q = (char*)d->ws;
     void* knn_ws = q;
@@ -902,8 +920,9 @@ int lagp_predict_mspe(const lagp_design* design, const double* XX, int64_t T, co
     for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
         const int64_t tc = std::min(kChunk, T - t0);
         const double* xx = XX + t0 * p;
+        const int32_t* mp = ncand_per ? ncand_per + t0 : nullptr;
         mark(-1);
-        r = lagp::knn_run(d->dev, xx, tc, M, nullptr, cand, M, false, knn_ws, knn_b, s, d->num_cu, d->max_lds, &err);
+        r = lagp::knn_run(d->dev, xx, tc, Mmax, mp, cand, Mmax, false, knn_ws, knn_b, s, d->num_cu, d->max_lds, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
         mark(LAGP_PHASE_KNN);
         lagp::MspeArgs a;
@@ -913,11 +932,13 @@ int lagp_predict_mspe(const lagp_design* design, const double* XX, int64_t T, co
         a.XX = xx;
         a.T = tc;
         a.cand = cand;
-        a.cand_stride = M;
+        a.cand_stride = Mmax;
+        a.n_per = n_per ? n_per + t0 : nullptr;
+        a.M_per = mp;
         a.n0 = prm->n0;
         a.n = prm->n;
-        a.M = M;
-        a.nmax = prm->n;
+        a.M = Mmax;
+        a.nmax = nmax;
         a.theta = prm->d;
         a.eta = prm->g;
         a.mean = mean + t0;

@@ -169,7 +169,9 @@ struct MspeArgs {
     int64_t T = 0;
     const int32_t* cand = nullptr;  // T x cand_stride candidate sets
     int64_t cand_stride = 0;
-    int n0 = 0, n = 0, M = 0, nmax = 0;
+    const int32_t* n_per = nullptr; // nullable: per-location design size (else n)
+    const int32_t* M_per = nullptr; // nullable: per-location candidate count (else M)
+    int n0 = 0, n = 0, M = 0, nmax = 0;   // M: the largest candidate count (sizes the slab)
     double theta = 1.0, eta = 0.0;
     double* mean = nullptr;
     double* s2 = nullptr;

@@ -45,7 +45,7 @@ constexpr int MAXWAVES = 8;           // reduction slots (up to 512 threads)
 constexpr int NSCAL = 16;             // location scalars in LDS
 
 enum {
-    S_PSI = 0, S_VX, S_T2, S_T3, S_Q, S_R, S_F, S_DMUX, S_DELTA, S_VS, S_D2XS, S_UI, S_WXI, S_HI, S_ZI, S_YS
+    S_PSI = 0, S_VX, S_T2, S_T3, S_Q, S_R, S_F, S_DMUX, S_VS, S_D2XS, S_UI, S_WXI, S_HI, S_ZI
 };
 
 __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }
@@ -115,8 +115,8 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
         __syncthreads();
         const int64_t t = ctl[0];
         if (t >= A.T) break;
-        const int n = A.n;
-        const int M = A.M;
+        const int n = A.n_per ? A.n_per[t] : A.n;
+        const int M = A.M_per ? A.M_per[t] : A.M;
         const int n0 = A.n0;
         const int32_t* cand = A.cand + t * A.cand_stride;
         for (int k = tid; k < p; k += MT) xl[k] = A.XX[t * p + k];
@@ -267,7 +267,6 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
                     sc[S_T3] += 2.0 * h_h + hi * hi;
                     sc[S_PSI] += ui * ui;
                     sc[S_VX] -= wxi * wxi;
-                    sc[S_DELTA] = delta;
                     sc[S_UI] = ui;
                     sc[S_WXI] = wxi;
                     sc[S_HI] = hi;

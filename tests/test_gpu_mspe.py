@@ -132,8 +132,30 @@ def test_mspe_invalid_arguments(lagp):
         D.predict_mspe(XX, 2, 10, 100, w.d, w.g)          # n0 < 3
     prm = lagp.lagp_params(6, 10, 100, w.d, w.g, lagp.LAGP_PREC_SCORE_FP32, 0)
     with pytest.raises(E):                                  # FP32 mode
-        lagp.lagp_predict_mspe(D.handle, XX, 4, prm, _dev(np.zeros(4)), _dev(np.zeros(4)), None, None, None, 0, None)
+        lagp.lagp_predict_mspe(D.handle, XX, 4, prm, None, None, _dev(np.zeros(4)), _dev(np.zeros(4)), None, None, None,
+                               0, None)
     w2 = workloads.c2(n=50, T=4)
     D2 = lagp.Design(w2.X, w2.y)
     with pytest.raises(E):
         D2.predict_mspe(_dev(w2.XX[:4]), 8, 50, 3000, w2.d, w2.g)   # more than 2048 candidates
+
+
+def test_mspe_per_location_sizes(lagp):
+    """Per-location design sizes and candidate counts in one call."""
+    import torch
+    w = workloads.c0()
+    D = lagp.Design(w.X, w.y)
+    T = 16
+    r = np.random.default_rng(9)
+    n_per = r.integers(6, 31, T).astype(np.int32)
+    M_per = r.integers(100, 700, T).astype(np.int32)
+    XX = w.XX[:T]
+    out = D.predict_mspe(_dev(XX), w.n0, 30, 700, w.d, 1e-3, n_per=_dev(n_per), ncand_per=_dev(M_per))
+    torch.cuda.synchronize()
+    res = {k: getattr(out, k).cpu().numpy() for k in ("mean", "s2", "df", "var", "sel", "status")}
+    for t in range(T):
+        rc, so, o, diag = oracle.mspe_local(w.X, w.y, XX[t], w.n0, int(n_per[t]), int(M_per[t]), w.d, 1e-3)
+        assert rc == 0 and res["status"][t] == 0
+        assert res["df"][t] == n_per[t]
+        assert np.array_equal(res["sel"][t, :n_per[t]], so), t
+        assert abs(res["mean"][t] - o[0]) <= 1e-9 * max(abs(o[0]), np.std(w.y))
