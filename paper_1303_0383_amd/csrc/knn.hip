@@ -17,13 +17,14 @@
 // keys inside the window to a small per-location bucket, which a finalise
 // kernel sorts to fill the remaining slots.
 //
-// Mapping: one thread per location, 256 locations per block.  The block
-// streams the design through an LDS tile (coalesced loads of the
-// coordinate-major copy) and every thread reads each tile point at a
-// wave-uniform LDS address (a broadcast).  Histograms are private per thread
-// in LDS, so no atomics are needed inside a block.  The design range can be
-// split over gridDim.y blocks to fill the chip when T is small; partial
-// histograms then meet in global memory through atomics.
+// Mapping: one thread per location, 256 locations per block.  Every lane of
+// a wave tests the same design row at a time, so the rows (row-major copy)
+// are read with wave-uniform addresses: scalar loads into SGPRs that feed the
+// FP64 subtractions directly, with no LDS staging, no LDS broadcast traffic
+// and no barriers in the scan.  Histograms are private per thread in LDS, so
+// no thread shares a counter inside a block.  The design range is split over
+// gridDim.y blocks to fill the chip; partial histograms then meet in global
+// memory through atomics.
 //
 // Squared distances are summed over coordinates left to right with no fused
 // multiply-add (this file is compiled with -ffp-contract=off).
@@ -39,9 +40,12 @@ typedef unsigned __int128 u128;
 
 #define KNN_THREADS 256
 #define KNN_BINS 64
-#define KNN_TILE 256
+#define KNN_TILE 256   // granule of a design split
 #define KNN_MAX_PASSES 18
 #define KNN_STAGE 16   // collected indices staged per thread before one slot reservation
+#define KNN_KSTAGE 8   // window keys staged per thread before one bucket-slot reservation
+#define KNN_COVER 16   // blocks per CU a split design aims for
+#define KNN_GROUP 4    // design rows whose distances are computed together
 
 struct KnnState {
     uint64_t lo_hi, lo_lo;   // window lower bound (128-bit key)
@@ -67,11 +71,11 @@ __device__ __forceinline__ int ceil_log2_128(u128 w)
     return s;
 }
 
-// Squared distance of an LDS tile point to x, left to right.  P > 0 is the
+// Squared distance of a design row to x, left to right.  P > 0 is the
 // dimension known at compile time (x in registers); P == 0 reads a runtime
 // dimension p with x kept in LDS.
 template <int P>
-__device__ __forceinline__ double tile_d2(const double* __restrict__ pt, const double* x, int p)
+__device__ __forceinline__ double row_d2(const double* __restrict__ pt, const double* x, int p)
 {
     double s = 0.0;
     if (P > 0) {
@@ -87,6 +91,26 @@ __device__ __forceinline__ double tile_d2(const double* __restrict__ pt, const d
         }
     }
     return s;
+}
+
+// Visit design rows [i0, i1) of the row-major Xa in index order, calling
+// f(d2, row) for each.  The row index is wave-uniform, so the row reads are
+// scalar loads; distances are computed KNN_GROUP rows at a time before any
+// of them is used, so the loads of a group are in flight together.
+template <int P, class F>
+__device__ __forceinline__ void scan_rows(const double* __restrict__ Xa, int64_t i0, int64_t i1,
+                                          const double* x, int p, F& f)
+{
+    const int64_t pp = P > 0 ? P : p;
+    int64_t i = i0;
+    for (; i + KNN_GROUP <= i1; i += KNN_GROUP) {
+        double d[KNN_GROUP];
+#pragma unroll
+        for (int u = 0; u < KNN_GROUP; ++u) d[u] = row_d2<P>(Xa + (i + u) * pp, x, p);
+#pragma unroll
+        for (int u = 0; u < KNN_GROUP; ++u) f(d[u], i + u);
+    }
+    for (; i < i1; ++i) f(row_d2<P>(Xa + i * pp, x, p), i);
 }
 
 // Pass 0 bin of a squared distance: its octave, clamped to [2^-51, 2^11).
@@ -133,28 +157,19 @@ __global__ void knn_init_kernel(KnnState* st, uint32_t* hist, int64_t T)
     for (int b = 0; b < KNN_BINS; ++b) hist[t * KNN_BINS + b] = 0;
 }
 
-// Load one tile of design points (coordinate-major source) into LDS as
-// point-major rows of p doubles.
-__device__ __forceinline__ void load_tile(double* tile, const double* __restrict__ Xsoa, int64_t N,
-                                          int p, int64_t base, int count)
-{
-    for (int k = 0; k < p; ++k)
-        for (int i = threadIdx.x; i < count; i += KNN_THREADS)
-            tile[i * p + k] = Xsoa[(int64_t)k * N + base + i];
-}
-
 // One histogram pass over design rows [i0, i1) for the 256 locations of this
 // block.  Pass kind is taken per location from its state.
 template <int P>
 __global__ void __launch_bounds__(KNN_THREADS)
-knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double* __restrict__ XX,
+knn_hist_kernel(const double* __restrict__ Xa, int64_t N, int p, const double* __restrict__ XX,
                 int64_t T, int32_t M, KnnState* __restrict__ st, uint32_t* __restrict__ hist,
                 uint32_t* __restrict__ belowc, int64_t chunk)
 {
     extern __shared__ double smem[];
-    double* tile = smem;                                          // KNN_TILE * p
-    uint16_t* h = (uint16_t*)(tile + (size_t)KNN_TILE * p);       // KNN_BINS * KNN_THREADS
-    __shared__ int any_active;
+    // Private histogram: two 16-bit counters per word (a split holds fewer
+    // than 65536 design rows, so no count carries into its neighbour), bumped
+    // with LDS atomic adds whose result is unused: no wait on an LDS read.
+    uint32_t* hw = (uint32_t*)smem;                               // KNN_BINS / 2 * KNN_THREADS
 
     const int tid = threadIdx.x;
     const int64_t t = (int64_t)blockIdx.x * KNN_THREADS + tid;
@@ -168,7 +183,7 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
     u128 lo = 0, hi = 0;
     int shift = 0;
     double xr[P > 0 ? P : 1];
-    double* xl = (double*)(h + KNN_BINS * KNN_THREADS) + tid;  // P == 0: x in LDS (8-byte aligned: 64*256*2 bytes)
+    double* xl = (double*)(hw + KNN_BINS / 2 * KNN_THREADS) + tid;  // P == 0: x in LDS
     const double* x = P > 0 ? xr : xl;
     if (t < T) {
         KnnState s = st[t];
@@ -186,14 +201,10 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
             for (int k = 0; k < p; ++k) xl[k * KNN_THREADS] = XX[t * p + k];
         }
     }
-    if (tid == 0) any_active = 0;
-    __syncthreads();
-    if (active) any_active = 1;
-    __syncthreads();
-    if (!any_active) return;
+    if (!active) return;   // (no barriers below)
 
-    for (int b = 0; b < KNN_BINS; ++b) h[b * KNN_THREADS + tid] = 0;
-    // (a split holds fewer than 65536 design rows, so 16-bit counters suffice)
+    for (int w = 0; w < KNN_BINS / 2; ++w) hw[w * KNN_THREADS + tid] = 0;
+    auto bump = [&](int b) { atomicAdd(hw + (b >> 1) * KNN_THREADS + tid, 1u << ((b & 1) << 4)); };
     const uint64_t lo_d = (uint64_t)(lo >> 31);
     const uint64_t hi_d = (uint64_t)((hi - 1) >> 31);
     // Window bounds on whole squared-distance values (the index bits zero)
@@ -202,51 +213,41 @@ knn_hist_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double*
     const u128 low31 = ((u128)1 << 31) - 1;
     const bool aligned = ((lo & low31) == 0) && ((hi & low31) == 0) && shift >= 31;
 
-    for (int64_t base = i0; base < i1; base += KNN_TILE) {
-        const int count = (int)((i1 - base) < KNN_TILE ? (i1 - base) : KNN_TILE);
-        __syncthreads();
-        load_tile(tile, Xsoa, N, p, base, count);
-        __syncthreads();
-        if (!active) continue;
-        if (kind == 0) {
-            for (int ii = 0; ii < count; ++ii) {
-                double d2 = tile_d2<P>(tile + ii * p, x, p);
-                int b = exp_bin((uint64_t)__double_as_longlong(d2));
-                h[b * KNN_THREADS + tid] += 1;
+    if (kind == 0) {
+        auto bin = [&](double d2, int64_t) {
+            bump(exp_bin((uint64_t)__double_as_longlong(d2)));
+        };
+        scan_rows<P>(Xa, i0, i1, x, p, bin);
+    } else {
+        auto bin = [&](double d2, int64_t gi) {
+            uint64_t bits = (uint64_t)__double_as_longlong(d2);
+            const bool under = bits < lo_d;
+            nbelow += (under && cbelow) ? 1u : 0u;
+            if (under || bits > hi_d) return;
+            int b;
+            if (aligned) {
+                // the window and its bins are whole distance values: 64-bit arithmetic
+                b = (int)((bits - lo_d) >> (shift - 31));
+            } else {
+                u128 key = ((u128)bits << 31) | (uint64_t)gi;
+                if (key < lo) { nbelow += cbelow ? 1u : 0u; return; }
+                if (key >= hi) return;
+                b = (int)((key - lo) >> shift);
             }
-        } else {
-            for (int ii = 0; ii < count; ++ii) {
-                double d2 = tile_d2<P>(tile + ii * p, x, p);
-                uint64_t bits = (uint64_t)__double_as_longlong(d2);
-                const bool under = bits < lo_d;
-                nbelow += (under && cbelow) ? 1u : 0u;
-                if (under || bits > hi_d) continue;
-                int b;
-                if (aligned) {
-                    // the window and its bins are whole distance values: 64-bit arithmetic
-                    b = (int)((bits - lo_d) >> (shift - 31));
-                } else {
-                    u128 key = ((u128)bits << 31) | (uint64_t)(base + ii);
-                    if (key < lo) { nbelow += cbelow ? 1u : 0u; continue; }
-                    if (key >= hi) continue;
-                    b = (int)((key - lo) >> shift);
-                }
-                h[b * KNN_THREADS + tid] += 1;
-            }
-        }
+            bump(b);
+        };
+        scan_rows<P>(Xa, i0, i1, x, p, bin);
     }
-    if (active && cbelow && nbelow) {
+    if (cbelow && nbelow) {
         if (gridDim.y == 1) belowc[t] += nbelow;
         else atomicAdd(belowc + t, nbelow);
     }
-    if (active) {
-        uint32_t* hg = hist + t * KNN_BINS;
-        for (int b = 0; b < KNN_BINS; ++b) {
-            uint32_t c = h[b * KNN_THREADS + tid];
-            if (c) {
-                if (gridDim.y == 1) hg[b] += c;
-                else atomicAdd(hg + b, c);
-            }
+    uint32_t* hg = hist + t * KNN_BINS;
+    for (int b = 0; b < KNN_BINS; ++b) {
+        uint32_t c = (hw[(b >> 1) * KNN_THREADS + tid] >> ((b & 1) << 4)) & 0xffffu;
+        if (c) {
+            if (gridDim.y == 1) hg[b] += c;
+            else atomicAdd(hg + b, c);
         }
     }
 }
@@ -379,17 +380,17 @@ __global__ void knn_estimate_kernel(KnnState* st, int64_t T, double fac)
 
 // Collect: keys below the window go to idx[t][*]; keys inside the window go
 // to the bucket with their full key.  When the design is split over several
-// blocks (gridDim.y > 1) a location's output slots are reserved with atomics,
-// KNN_STAGE indices at a time from a per-thread LDS stage.
+// blocks (gridDim.y > 1) a location's output and bucket slots are reserved
+// with atomics, KNN_STAGE indices or KNN_KSTAGE keys at a time from
+// per-thread LDS stages, so no row waits on an atomic's result.
 template <int P>
 __global__ void __launch_bounds__(KNN_THREADS)
-knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const double* __restrict__ XX,
+knn_collect_kernel(const double* __restrict__ Xa, int64_t N, int p, const double* __restrict__ XX,
                    int64_t T, const KnnState* __restrict__ st, uint32_t* __restrict__ counts,
                    int32_t* __restrict__ idx, int64_t idx_stride, uint64_t* __restrict__ bucket,
                    int32_t bucket_max, int64_t chunk)
 {
     extern __shared__ double smem[];
-    double* tile = smem;
     const int tid = threadIdx.x;
     const int64_t t = (int64_t)blockIdx.x * KNN_THREADS + tid;
     const int64_t i0 = (int64_t)blockIdx.y * chunk;
@@ -399,9 +400,12 @@ knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const doub
     bool active = t < T;
     u128 lo = 0, hi = 0;
     double xr[P > 0 ? P : 1];
-    double* xl = tile + (size_t)KNN_TILE * p + tid;  // P == 0: x in LDS
-    int32_t* stage = (int32_t*)(tile + (size_t)KNN_TILE * p + (P > 0 ? 0 : (size_t)KNN_THREADS * p));
+    double* xl = smem + tid;  // P == 0: x in LDS
+    int32_t* stage = (int32_t*)(smem + (P > 0 ? 0 : (size_t)KNN_THREADS * p));
+    uint64_t* kbits = (uint64_t*)(stage + KNN_STAGE * KNN_THREADS);   // staged window keys: distance bits
+    uint32_t* kidx = (uint32_t*)(kbits + KNN_KSTAGE * KNN_THREADS);   // and design index
     int ns = 0;   // staged indices of this thread
+    int nk = 0;   // staged window keys of this thread
     const double* x = P > 0 ? xr : xl;
     uint32_t nbelow = 0, nbkt = 0;
     if (active) {
@@ -417,50 +421,59 @@ knn_collect_kernel(const double* __restrict__ Xsoa, int64_t N, int p, const doub
     }
     const uint64_t lo_d = (uint64_t)(lo >> 31);
     const uint64_t hi_d = (uint64_t)((hi - 1) >> 31);
-    int32_t* out = active ? idx + t * idx_stride : nullptr;
-    uint64_t* bk = active ? bucket + t * (int64_t)bucket_max * 2 : nullptr;
-
-    for (int64_t base = i0; base < i1; base += KNN_TILE) {
-        const int count = (int)((i1 - base) < KNN_TILE ? (i1 - base) : KNN_TILE);
-        __syncthreads();
-        load_tile(tile, Xsoa, N, p, base, count);
-        __syncthreads();
-        if (!active) continue;
-        for (int ii = 0; ii < count; ++ii) {
-            double d2 = tile_d2<P>(tile + ii * p, x, p);
-            uint64_t bits = (uint64_t)__double_as_longlong(d2);
-            if (bits > hi_d) continue;
-            const int64_t gi = base + ii;
-            // the full key only at or above the window's first distance value
-            const bool under = bits < lo_d;
-            u128 key = 0;
-            if (!under) key = ((u128)bits << 31) | (uint64_t)gi;
-            if (under || key < lo) {
-                if (!split) {
-                    out[nbelow++] = (int32_t)gi;
-                } else {
-                    stage[ns * KNN_THREADS + tid] = (int32_t)gi;
-                    if (++ns == KNN_STAGE) {
-                        const uint32_t b0 = atomicAdd(counts + 2 * t, (uint32_t)KNN_STAGE);
+    if (!active) return;   // (no barriers below)
+    int32_t* out = idx + t * idx_stride;
+    uint64_t* bk = bucket + t * (int64_t)bucket_max * 2;
+    auto put = [&](uint32_t slot, uint64_t bits, uint32_t gi) {
+        if (slot < (uint32_t)bucket_max) {
+            const u128 key = ((u128)bits << 31) | gi;
+            bk[2 * slot] = hi64(key);
+            bk[2 * slot + 1] = lo64(key);
+        }
+    };
+    auto flush_keys = [&](int n) {
+        const uint32_t b0 = atomicAdd(counts + 2 * t + 1, (uint32_t)n);
+        for (int j = 0; j < n; ++j) put(b0 + j, kbits[j * KNN_THREADS + tid], kidx[j * KNN_THREADS + tid]);
+    };
+    auto take = [&](double d2, int64_t gi) {
+        uint64_t bits = (uint64_t)__double_as_longlong(d2);
+        if (bits > hi_d) return;
+        // the full key only at or above the window's first distance value
+        const bool under = bits < lo_d;
+        u128 key = 0;
+        if (!under) key = ((u128)bits << 31) | (uint64_t)gi;
+        if (under || key < lo) {
+            if (!split) {
+                out[nbelow++] = (int32_t)gi;
+            } else {
+                stage[ns * KNN_THREADS + tid] = (int32_t)gi;
+                if (++ns == KNN_STAGE) {
+                    const uint32_t b0 = atomicAdd(counts + 2 * t, (uint32_t)KNN_STAGE);
 #pragma unroll
-                        for (int j = 0; j < KNN_STAGE; ++j) out[b0 + j] = stage[j * KNN_THREADS + tid];
-                        ns = 0;
-                    }
+                    for (int j = 0; j < KNN_STAGE; ++j) out[b0 + j] = stage[j * KNN_THREADS + tid];
+                    ns = 0;
                 }
-            } else if (key < hi) {
-                uint32_t slot = split ? atomicAdd(counts + 2 * t + 1, 1u) : nbkt++;
-                if (slot < (uint32_t)bucket_max) {
-                    bk[2 * slot] = hi64(key);
-                    bk[2 * slot + 1] = lo64(key);
+            }
+        } else if (key < hi) {
+            if (!split) {
+                put(nbkt++, bits, (uint32_t)gi);
+            } else {
+                kbits[nk * KNN_THREADS + tid] = bits;
+                kidx[nk * KNN_THREADS + tid] = (uint32_t)gi;
+                if (++nk == KNN_KSTAGE) {
+                    flush_keys(KNN_KSTAGE);
+                    nk = 0;
                 }
             }
         }
-    }
-    if (split && active && ns > 0) {
+    };
+    scan_rows<P>(Xa, i0, i1, x, p, take);
+    if (split && ns > 0) {
         const uint32_t b0 = atomicAdd(counts + 2 * t, (uint32_t)ns);
         for (int j = 0; j < ns; ++j) out[b0 + j] = stage[j * KNN_THREADS + tid];
     }
-    if (!split && active) {
+    if (split && nk > 0) flush_keys(nk);
+    if (!split) {
         counts[2 * t] = nbelow;
         counts[2 * t + 1] = nbkt;
     }
@@ -583,11 +596,11 @@ size_t knn_workspace_bytes(int64_t T, int32_t bucket_max)
 }
 
 // Split a design of N rows over gridDim.y so that the grid covers the chip
-// about four times over, keeping at least 2 tiles per split and at most
+// about KNN_COVER times over, keeping at least 2 granules per split and at most
 // 65280 rows per split (16-bit private histogram counters).
 static void knn_split(int64_t N, int64_t nblk, int num_cu, int64_t* chunk_out, int64_t* split_out)
 {
-    int64_t split = (4LL * num_cu + nblk - 1) / nblk;
+    int64_t split = ((int64_t)KNN_COVER * num_cu + nblk - 1) / nblk;
     int64_t max_split = (N + 2 * KNN_TILE - 1) / (2 * KNN_TILE);
     if (split > max_split) split = max_split;
     if (split < 1) split = 1;
@@ -603,15 +616,16 @@ static void knn_split(int64_t N, int64_t nblk, int num_cu, int64_t* chunk_out, i
 static void knn_lds(int p, size_t* lds_hist, size_t* lds_coll)
 {
     const size_t lds_x = p <= 8 ? 0 : (size_t)KNN_THREADS * p * sizeof(double);
-    *lds_hist = (size_t)KNN_TILE * p * sizeof(double) + (size_t)KNN_BINS * KNN_THREADS * 2 + lds_x;
-    *lds_coll = (size_t)KNN_TILE * p * sizeof(double) + lds_x + (size_t)KNN_STAGE * KNN_THREADS * sizeof(int32_t);
+    *lds_hist = (size_t)KNN_BINS * KNN_THREADS * 2 + lds_x;
+    *lds_coll = lds_x + (size_t)KNN_STAGE * KNN_THREADS * sizeof(int32_t) +
+                (size_t)KNN_KSTAGE * KNN_THREADS * (sizeof(uint64_t) + sizeof(uint32_t));
 }
 
 int knn_prepare(int p, size_t max_lds, std::string* err)
 {
     size_t lds_hist, lds_coll;
     knn_lds(p, &lds_hist, &lds_coll);
-    if (lds_hist > max_lds) { *err = "input dimension too large for the kNN tile"; return -1; }
+    if (lds_hist > max_lds || lds_coll > max_lds) { *err = "input dimension too large for the kNN kernels"; return -1; }
 #define LAGP_KNN_ATTR(PP)                                                                              \
     if (!set_lds_limit((const void*)knn_hist_kernel<PP>, max_lds) ||                                 \
         !set_lds_limit((const void*)knn_collect_kernel<PP>, max_lds)) {                               \
@@ -644,12 +658,12 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     // Estimate each location's candidate radius on the design sample first
     // when the sample holds enough rows (two cheap passes replace the first
     // full octave pass).
-    const bool use_sample = D.Xsoa_s && D.Ns >= 2 * KNN_TILE && (int64_t)M * 8 <= D.N;
+    const bool use_sample = D.Xaos_s && D.Ns >= 2 * KNN_TILE && (int64_t)M * 8 <= D.N;
     const double fac = pow(3.0, 2.0 / D.p);   // 3^(2/p)
     if (use_sample) knn_split(D.Ns, nblk, num_cu, &chunk_s, &split_s);
     size_t lds_hist, lds_coll;
     knn_lds(D.p, &lds_hist, &lds_coll);
-    if (lds_hist > max_lds) { *err = "input dimension too large for the kNN tile"; return -1; }
+    if (lds_hist > max_lds || lds_coll > max_lds) { *err = "input dimension too large for the kNN kernels"; return -1; }
     if (!graph_safe && knn_prepare(D.p, max_lds, err)) return -2;
 
     hipLaunchKernelGGL(knn_init_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, st, hist, T);
@@ -663,7 +677,7 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
         const dim3 grid_s((unsigned)nblk, (unsigned)split_s);
         for (int pass = 0; pass < 2; ++pass) {
 #define LAGP_KNN_HIST(PP) hipLaunchKernelGGL(knn_hist_kernel<PP>, grid_s, dim3(KNN_THREADS), lds_hist, stream, \
-                                             D.Xsoa_s, D.Ns, D.p, XX, T, M, st, hist, belowc, chunk_s)
+                                             D.Xaos_s, D.Ns, D.p, XX, T, M, st, hist, belowc, chunk_s)
             LAGP_DISPATCH_P(D.p, LAGP_KNN_HIST);
 #undef LAGP_KNN_HIST
             hipLaunchKernelGGL(knn_decide_kernel, dim3(dgrid), dim3(256), 0, stream, st, hist, belowc, T, M, M_per,
@@ -679,7 +693,7 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     // blocks whose locations have settled return at once.
     for (int pass = 0; pass < KNN_MAX_PASSES; ++pass) {
 #define LAGP_KNN_HIST(PP) hipLaunchKernelGGL(knn_hist_kernel<PP>, grid, dim3(KNN_THREADS), lds_hist, stream, \
-                                             D.Xsoa, D.N, D.p, XX, T, M, st, hist, belowc, chunk)
+                                             D.Xaos, D.N, D.p, XX, T, M, st, hist, belowc, chunk)
         LAGP_DISPATCH_P(D.p, LAGP_KNN_HIST);
 #undef LAGP_KNN_HIST
         fill_u32(flags, 1, 0u, stream);
@@ -697,7 +711,7 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     }
     fill_u32(counts, T * 2, 0u, stream);
 #define LAGP_KNN_COLL(PP) hipLaunchKernelGGL(knn_collect_kernel<PP>, grid, dim3(KNN_THREADS), lds_coll, stream, \
-                                             D.Xsoa, D.N, D.p, XX, T, st, counts, idx, idx_stride, bucket, \
+                                             D.Xaos, D.N, D.p, XX, T, st, counts, idx, idx_stride, bucket, \
                                              bucket_max, chunk)
     LAGP_DISPATCH_P(D.p, LAGP_KNN_COLL);
 #undef LAGP_KNN_COLL

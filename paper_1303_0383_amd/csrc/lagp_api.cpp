@@ -44,23 +44,14 @@ bool is_device_ptr(const void* p)
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-__global__ void aos_to_soa_kernel(const double* __restrict__ aos, double* __restrict__ soa, int64_t N, int p)
-{
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= N * p) return;
-    int64_t i = e / p;
-    int k = (int)(e - i * p);
-    soa[(int64_t)k * N + i] = aos[e];
-}
-
-// Rows 0, S, 2S, ... of the row-major design into a coordinate-major sample.
-__global__ void sample_soa_kernel(const double* __restrict__ aos, double* __restrict__ soa, int64_t Ns, int p, int S)
+// Rows 0, S, 2S, ... of the row-major design into a row-major sample.
+__global__ void sample_rows_kernel(const double* __restrict__ X, double* __restrict__ Xs, int64_t Ns, int p, int S)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= Ns * p) return;
     int64_t j = e / p;
     int k = (int)(e - j * p);
-    soa[(int64_t)k * Ns + j] = aos[j * S * p + k];
+    Xs[e] = X[j * S * p + k];
 }
 
 int ensure_ws(lagp_design* d, size_t bytes, hipStream_t stream)
@@ -137,8 +128,8 @@ int lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, u
     d->max_lds = prop.sharedMemPerBlock;
     const size_t bytes = (size_t)N * p * sizeof(double);
     const int64_t Ns = (N + lagp::KNN_SAMPLE_STRIDE - 1) / lagp::KNN_SAMPLE_STRIDE;
-    if (hipMalloc(&d->Xaos, bytes) != hipSuccess || hipMalloc(&d->Xsoa, bytes) != hipSuccess ||
-        hipMalloc(&d->Xsoa_s, (size_t)Ns * p * sizeof(double)) != hipSuccess ||
+    if (hipMalloc(&d->Xaos, bytes) != hipSuccess ||
+        hipMalloc(&d->Xaos_s, (size_t)Ns * p * sizeof(double)) != hipSuccess ||
         hipMalloc(&d->y, (size_t)N * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         lagp_design_destroy(d);
@@ -148,17 +139,13 @@ int lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, u
     e = hipMemcpyAsync(d->Xaos, X, bytes, kind, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d->y, y, (size_t)N * sizeof(double), kind, s);
     if (e != hipSuccess) { lagp_design_destroy(d); return hip_fail("design copy", e); }
-    const int64_t tot = N * p;
-    hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d->Xaos,
-                       d->Xsoa, N, p);
-    hipLaunchKernelGGL(sample_soa_kernel, dim3((unsigned)((Ns * p + 255) / 256)), dim3(256), 0, s, d->Xaos,
-                       d->Xsoa_s, Ns, p, lagp::KNN_SAMPLE_STRIDE);
+    hipLaunchKernelGGL(sample_rows_kernel, dim3((unsigned)((Ns * p + 255) / 256)), dim3(256), 0, s, d->Xaos,
+                       d->Xaos_s, Ns, p, lagp::KNN_SAMPLE_STRIDE);
     e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) { lagp_design_destroy(d); return hip_fail("design layout", e); }
     d->dev.Xaos = d->Xaos;
-    d->dev.Xsoa = d->Xsoa;
-    d->dev.Xsoa_s = d->Xsoa_s;
+    d->dev.Xaos_s = d->Xaos_s;
     d->dev.Ns = Ns;
     d->dev.y = d->y;
     d->dev.N = N;
@@ -173,8 +160,7 @@ void lagp_design_destroy(lagp_design* d)
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
     if (d->Xaos) (void)hipFree(d->Xaos);
-    if (d->Xsoa) (void)hipFree(d->Xsoa);
-    if (d->Xsoa_s) (void)hipFree(d->Xsoa_s);
+    if (d->Xaos_s) (void)hipFree(d->Xaos_s);
     if (d->y) (void)hipFree(d->y);
     if (d->ws) (void)hipFree(d->ws);
     delete d;

@@ -24,14 +24,13 @@ inline bool set_lds_limit(const void* kernel, size_t max_lds)
 }
 
 struct DeviceDesign {
-    const double* Xsoa = nullptr;  // p x N
     const double* Xaos = nullptr;  // N x p
     const double* y = nullptr;     // N
     int64_t N = 0;
     int32_t p = 0;
-    // Every KNN_SAMPLE_STRIDE-th design row, p x Ns (the kNN estimates each
-    // location's candidate radius on it); nullptr when not built.
-    const double* Xsoa_s = nullptr;
+    // Every KNN_SAMPLE_STRIDE-th design row, Ns x p row-major (the kNN
+    // estimates each location's candidate radius on it); nullptr when not built.
+    const double* Xaos_s = nullptr;
     int64_t Ns = 0;
 };
 

@@ -17,8 +17,7 @@ struct lagp_design {
     int device = 0;
     int num_cu = 0;
     size_t max_lds = 0;
-    double* Xsoa = nullptr;
-    double* Xsoa_s = nullptr;   // strided sample of the design rows, coordinate-major
+    double* Xaos_s = nullptr;   // strided sample of the design rows, row-major
     double* Xaos = nullptr;
     double* y = nullptr;
     void* ws = nullptr;
