@@ -84,6 +84,24 @@ def test_knn_ties_grid(lagp):
             assert np.array_equal(idx[t], ref), (M, t)
 
 
+@pytest.mark.parametrize("p", [3, 8, 12])
+def test_knn_ragged_rows(lagp, p):
+    """Design sizes whose last rows do not fill a group of four rows, split
+    over several blocks (and estimated on a sample whose size is ragged too),
+    with a location count that does not fill a block; p = 12 takes the
+    runtime-dimension path."""
+    r = np.random.default_rng(300 + p)
+    for N in (4099, 70001):
+        X = r.uniform(0.0, 1.0, (N, p))
+        D = lagp.Design(X, np.zeros(N))
+        XX = r.uniform(0.0, 1.0, (77, p))
+        for M in (1, 37, 1000):
+            idx = _knn_gpu(D, XX, M)
+            for t in range(0, 77, 11):
+                ref, _ = oracle.knn(X, XX[t], M)
+                assert np.array_equal(idx[t], ref), (N, M, t)
+
+
 @pytest.mark.parametrize("layout", ["far_sample", "near_sample", "duplicates"])
 def test_knn_unrepresentative_sample(lagp, layout):
     """The kNN first estimates each location's candidate radius on every 16th
