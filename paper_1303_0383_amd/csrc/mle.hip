@@ -52,19 +52,24 @@ namespace {
 constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product
 constexpr int NRED = 7; // sums reduced per iterate
 
-__device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }   // lower, diagonal included
-__device__ __forceinline__ int sl(int i, int k) { return i * (i - 1) / 2 + k; }    // strictly lower, i > k
+// Packed indices.  Every index here is far below 2^24, so the products use
+// the full-rate 24-bit multiply instead of the quarter-rate 32-bit one.
+__device__ __forceinline__ int half_prod(int a, int b) { return (int)(__umul24((unsigned)a, (unsigned)b) >> 1); }
+__device__ __forceinline__ int tri(int i, int k) { return half_prod(i, i + 1) + k; }   // lower, diagonal included
+__device__ __forceinline__ int sl(int i, int k) { return half_prod(i, i - 1) + k; }    // strictly lower, i > k
 
 // Row of packed-lower index e (a(a+1)/2 <= e < (a+1)(a+2)/2).  The float
 // estimate is within one of the row for every index a design of up to a few
 // hundred points has, so one branch-free correction each way suffices (a
 // loop here compiles to far more instructions than the multiply-add it
-// feeds).
+// feeds).  The hardware square root (about 1 ulp) is used directly: the
+// corrections absorb its error, and the correctly rounded sqrtf costs a
+// dozen more instructions per call.
 __device__ __forceinline__ int row_of(int e)
 {
-    int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-    a -= (a * (a + 1) / 2 > e) ? 1 : 0;
-    a += ((a + 1) * (a + 2) / 2 <= e) ? 1 : 0;
+    int a = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    a -= (half_prod(a, a + 1) > e) ? 1 : 0;
+    a += (half_prod(a + 1, a + 2) <= e) ? 1 : 0;
     return a;
 }
 
@@ -143,7 +148,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             const double th2 = theta * theta;
             // ---- K and dK
             for (int e = tid; e < ntri; e += MT) {
-                const int a = row_of(e), b = e - a * (a + 1) / 2;
+                const int a = row_of(e), b = e - half_prod(a, a + 1);
                 if (a == b) {
                     Tm[e] = 1.0 + A.eta;
                 } else {
@@ -173,7 +178,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 // trailing triangle rows i > m, columns m < k <= i; and u
                 const int tn = n - m - 1;
                 for (int e = tid; e < tn * (tn + 1) / 2; e += MT) {
-                    const int ii = row_of(e), kk = e - ii * (ii + 1) / 2;
+                    const int ii = row_of(e), kk = e - half_prod(ii, ii + 1);
                     const int i = m + 1 + ii, k = m + 1 + kk;
                     Tm[tri(i, k)] -= (Tm[tri(i, m)] * Tm[tri(k, m)]) * rpm;
                 }
@@ -223,14 +228,23 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             // ---- w = L^{-T} u, then k = dK w
             for (int b = tid; b < n; b += MT) {
                 double s = 0.0;
-                for (int a = b; a < n; ++a) s += Tm[tri(a, b)] * u[a];
+                int o = tri(b, b);                 // (a, b), a = b, b + 1, ...: steps of a + 1
+                for (int a = b; a < n; ++a) {
+                    s += Tm[o] * u[a];
+                    o += a + 1;
+                }
                 w[b] = s;
             }
             __syncthreads();
             for (int a = tid; a < n; a += MT) {
                 double s = 0.0;
-                for (int b = 0; b < a; ++b) s += Cd[sl(a, b)] * w[b];
-                for (int b = a + 1; b < n; ++b) s += Cd[sl(b, a)] * w[b];
+                const double* ca = Cd + sl(a, 0);
+                for (int b = 0; b < a; ++b) s += ca[b] * w[b];
+                int o = sl(a + 1, a);              // (b, a), b = a + 1, ...: steps of b
+                for (int b = a + 1; b < n; ++b) {
+                    s += Cd[o] * w[b];
+                    o += b;
+                }
                 kw[a] = s;
             }
             __syncthreads();
@@ -240,16 +254,22 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 acc[0] += u[a] * u[a];
                 acc[1] += w[a] * kw[a];
                 double z = 0.0;
-                for (int b = 0; b <= a; ++b) z += Tm[tri(a, b)] * kw[b];
+                const double* la = Tm + tri(a, 0);
+                for (int b = 0; b <= a; ++b) z += la[b] * kw[b];
                 acc[2] += z * z;
             }
             // off-diagonal pairs a > b: K^{-1}_ab = sum_{k >= a} Li_ka Li_kb
             const double r2t = 2.0 / theta;
             const int nsl = n * (n - 1) / 2;
             for (int e = tid; e < nsl; e += MT) {
-                const int a = row_of(e) + 1, b = e - a * (a - 1) / 2;
+                const int a = row_of(e) + 1, b = e - half_prod(a, a - 1);
                 double ki = 0.0;
-                for (int k = a; k < n; ++k) ki += Tm[tri(k, a)] * Tm[tri(k, b)];
+                int oa = tri(a, a), ob = tri(a, b);   // rows k = a, a + 1, ...: steps of k + 1
+                for (int k = a; k < n; ++k) {
+                    ki += Tm[oa] * Tm[ob];
+                    oa += k + 1;
+                    ob += k + 1;
+                }
                 const double kd = Cd[e];
                 const double d2 = sqdist_rows(xs, a, b, p);
                 const double kdd = kd * (d2 / th2 - r2t);
@@ -265,14 +285,21 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 if (ph < np) {
                     const int j0 = ph * PW, pw = (n - j0) < PW ? (n - j0) : PW;
                     double* H = Hb + (size_t)(ph & 1) * nm * PW;
-                    // H[a][jj] = sum_{b <= j} dK_ab Li_jb, j = j0 + jj
+                    // H[a][jj] = sum_{b <= j} dK_ab Li_jb, j = j0 + jj, in ascending
+                    // b: row a of the strictly-lower dK for b < a, then column a
+                    // (dK_aa = 0 adds nothing)
                     for (int e = tid; e < n * PW; e += MT) {
                         const int a = e / PW, jj = e % PW, j = j0 + jj;
                         if (jj >= pw) continue;
+                        const double* lj = Tm + tri(j, 0);
+                        const double* ca = Cd + sl(a, 0);
                         double s = 0.0;
-                        for (int b = 0; b <= j; ++b) {
-                            const double kd = (a > b) ? Cd[sl(a, b)] : (a < b ? Cd[sl(b, a)] : 0.0);
-                            s += kd * Tm[tri(j, b)];
+                        const int b1 = a < j + 1 ? a : j + 1;
+                        for (int b = 0; b < b1; ++b) s += ca[b] * lj[b];
+                        int o = sl(a + 1, a);
+                        for (int b = a + 1; b <= j; ++b) {
+                            s += Cd[o] * lj[b];
+                            o += b;
                         }
                         H[a * PW + jj] = s;
                     }
@@ -285,7 +312,8 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                         const int i = e / PW, jj = e % PW, j = j0 + jj;
                         if (jj >= pw || i < j) continue;
                         double s = 0.0;
-                        for (int a = 0; a <= i; ++a) s += Tm[tri(i, a)] * H[a * PW + jj];
+                        const double* li = Tm + tri(i, 0);
+                        for (int a = 0; a <= i; ++a) s += li[a] * H[a * PW + jj];
                         acc[6] += (i == j ? 1.0 : 2.0) * (s * s);
                     }
                 }
