@@ -159,16 +159,20 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 }
             }
             for (int a = tid; a < n; a += MT) u[a] = yv[a];
+            if (tid == 0) red[0] = 1.0 / Tm[0];   // thread 0 wrote Tm[0] (item 0) above
             __syncthreads();
             // ---- Cholesky, right-looking, one barrier per column: the pivot
             //      column m is used unscaled (products divided by the pivot) and
             //      scaled in place during column m+1's phase, when nothing reads
             //      it; u = L^{-1} Y is carried the same way.
+            // The reciprocal of each pivot is formed once, by thread 0, which
+            // also updates the next pivot (trailing item 0), and passed on in
+            // red[0..1] (free until the sums at the end of the iterate).
             int fail = 0;
             for (int m = 0; m < n; ++m) {
                 const double pm = Tm[tri(m, m)];
                 if (!(pm > 0.0)) { fail = 1; break; }   // uniform: every thread read the same pivot
-                const double rpm = 1.0 / pm;
+                const double rpm = red[m & 1];
                 if (m > 0) {
                     const double dp = piv[m - 1];
                     for (int i = m + tid; i < n; i += MT) Tm[tri(i, m - 1)] = Tm[tri(i, m - 1)] / dp;
@@ -184,6 +188,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 }
                 const double um = u[m];
                 for (int i = m + 1 + tid; i < n; i += MT) u[i] -= (Tm[tri(i, m)] * um) * rpm;
+                if (tid == 0 && m + 1 < n) red[(m + 1) & 1] = 1.0 / Tm[tri(m + 1, m + 1)];
                 __syncthreads();
             }
             if (fail) {
@@ -195,14 +200,16 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             //      used unscaled (times 1/L_kk on the fly) and scaled during the
             //      next phase; column k+1 of L is copied aside in phase k (two
             //      buffers), before phase k+1 overwrites it.
+            double* rpv = w;   // 1 / L_kk (w is free until w = L^{-T} u)
             for (int i = 1 + tid; i < n; i += MT) col[i] = Tm[tri(i, 0)];
+            for (int i = tid; i < n; i += MT) rpv[i] = 1.0 / piv[i];
             __syncthreads();
             for (int k = 0; k < n; ++k) {
-                const double rk = 1.0 / piv[k];
+                const double rk = rpv[k];
                 const double* ck = (k & 1) ? col2 : col;
                 double* cn = (k & 1) ? col : col2;
                 if (k > 0) {
-                    const double rp = 1.0 / piv[k - 1];
+                    const double rp = rpv[k - 1];
                     for (int c = tid; c < k - 1; c += MT) Tm[tri(k - 1, c)] = Tm[tri(k - 1, c)] * rp;
                     if (tid == 0) Tm[tri(k - 1, k - 1)] = rp;
                 }
@@ -220,7 +227,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 __syncthreads();
             }
             {
-                const double rp = 1.0 / piv[n - 1];
+                const double rp = rpv[n - 1];
                 for (int c = tid; c < n - 1; c += MT) Tm[tri(n - 1, c)] = Tm[tri(n - 1, c)] * rp;
                 if (tid == 0) Tm[tri(n - 1, n - 1)] = rp;
             }
