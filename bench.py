@@ -258,6 +258,23 @@ def main() -> int:
         "roofline": roofline,
     }
 
+    if alc2:
+        # Newton iterates of the two likelihood passes, measured outside the
+        # timed region by repeating them through lagp_mle (same kernel, same
+        # designs and starting values): the MLE from d0 of the designs at d0,
+        # and the MLE from theta1 of the second designs.
+        first = D.predict(XX, w.n0, nmax, Mmax, w.d, w.g, n_per=n_per, ncand_per=M_per, precision=prec)
+        _, it1, _ = D.mle(first.sel, w.d, w.g, tmin, tmax, n_per=n_per)
+        _, it2, _ = D.mle(out.sel, out.theta1, w.g, tmin, tmax, n_per=n_per)
+        torch.cuda.synchronize()
+        n_it = int(it1.sum().item()) + int(it2.sum().item())
+        mle_ms = phase.get("mle", 0.0) / args.steps
+        result["mle"] = {"iterates_from_d0": round(float(it1.double().mean().item()), 3),
+                         "iterates_from_theta1": round(float(it2.double().mean().item()), 3),
+                         "location_iterates_per_step": n_it,
+                         "ns_per_location_iterate": round(mle_ms * 1e6 / max(n_it, 1), 2)}
+        del first
+
     res = {k: getattr(out, k).cpu().numpy() for k in ("mean", "s2", "df", "var", "sel", "status")}
     rng = np.random.default_rng(20130383)
 
