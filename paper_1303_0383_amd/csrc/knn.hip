@@ -44,7 +44,8 @@ typedef unsigned __int128 u128;
 #define KNN_MAX_PASSES 18
 #define KNN_STAGE 16   // collected indices staged per thread before one slot reservation
 #define KNN_KSTAGE 8   // window keys staged per thread before one bucket-slot reservation
-#define KNN_COVER 16   // blocks per CU a split design aims for
+#define KNN_COVER 32   // blocks per CU a split design aims for
+#define KNN_MIN_CHUNK 8 // granules of KNN_TILE rows per split, at least
 #define KNN_GROUP 4    // design rows whose distances are computed together
 
 struct KnnState {
@@ -596,12 +597,12 @@ size_t knn_workspace_bytes(int64_t T, int32_t bucket_max)
 }
 
 // Split a design of N rows over gridDim.y so that the grid covers the chip
-// about KNN_COVER times over, keeping at least 2 granules per split and at most
+// about KNN_COVER times over, keeping at least KNN_MIN_CHUNK granules per split and at most
 // 65280 rows per split (16-bit private histogram counters).
 static void knn_split(int64_t N, int64_t nblk, int num_cu, int64_t* chunk_out, int64_t* split_out)
 {
     int64_t split = ((int64_t)KNN_COVER * num_cu + nblk - 1) / nblk;
-    int64_t max_split = (N + 2 * KNN_TILE - 1) / (2 * KNN_TILE);
+    int64_t max_split = (N + KNN_MIN_CHUNK * KNN_TILE - 1) / (KNN_MIN_CHUNK * KNN_TILE);
     if (split > max_split) split = max_split;
     if (split < 1) split = 1;
     if (split > 65535) split = 65535;
