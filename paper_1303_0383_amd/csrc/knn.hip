@@ -40,12 +40,12 @@ typedef unsigned __int128 u128;
 
 #define KNN_THREADS 256
 #define KNN_BINS 64
-#define KNN_TILE 256   // granule of a design split
+#define KNN_GRANULE 256 // rows: a design split is a multiple of this
 #define KNN_MAX_PASSES 18
 #define KNN_STAGE 16   // collected indices staged per thread before one slot reservation
 #define KNN_KSTAGE 8   // window keys staged per thread before one bucket-slot reservation
 #define KNN_COVER 32   // blocks per CU a split design aims for
-#define KNN_MIN_CHUNK 8 // granules of KNN_TILE rows per split, at least
+#define KNN_MIN_CHUNK 8 // granules per split, at least
 #define KNN_GROUP 4    // design rows whose distances are computed together
 
 struct KnnState {
@@ -602,14 +602,14 @@ size_t knn_workspace_bytes(int64_t T, int32_t bucket_max)
 static void knn_split(int64_t N, int64_t nblk, int num_cu, int64_t* chunk_out, int64_t* split_out)
 {
     int64_t split = ((int64_t)KNN_COVER * num_cu + nblk - 1) / nblk;
-    int64_t max_split = (N + KNN_MIN_CHUNK * KNN_TILE - 1) / (KNN_MIN_CHUNK * KNN_TILE);
+    int64_t max_split = (N + KNN_MIN_CHUNK * KNN_GRANULE - 1) / (KNN_MIN_CHUNK * KNN_GRANULE);
     if (split > max_split) split = max_split;
     if (split < 1) split = 1;
     if (split > 65535) split = 65535;
     const int64_t max_chunk = 65280;
     if (split < (N + max_chunk - 1) / max_chunk) split = (N + max_chunk - 1) / max_chunk;
     int64_t chunk = (N + split - 1) / split;
-    chunk = (chunk + KNN_TILE - 1) / KNN_TILE * KNN_TILE;
+    chunk = (chunk + KNN_GRANULE - 1) / KNN_GRANULE * KNN_GRANULE;
     *chunk_out = chunk;
     *split_out = (N + chunk - 1) / chunk;
 }
@@ -659,7 +659,7 @@ int knn_run(const DeviceDesign& D, const double* XX, int64_t T, int32_t M, const
     // Estimate each location's candidate radius on the design sample first
     // when the sample holds enough rows (two cheap passes replace the first
     // full octave pass).
-    const bool use_sample = D.Xaos_s && D.Ns >= 2 * KNN_TILE && (int64_t)M * 8 <= D.N;
+    const bool use_sample = D.Xaos_s && D.Ns >= 2 * KNN_GRANULE && (int64_t)M * 8 <= D.N;
     const double fac = pow(3.0, 2.0 / D.p);   // 3^(2/p)
     if (use_sample) knn_split(D.Ns, nblk, num_cu, &chunk_s, &split_s);
     size_t lds_hist, lds_coll;
