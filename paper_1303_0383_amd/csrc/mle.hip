@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             if (tid == 0) red[0] = 1.0 / Tm[0];   // thread 0 wrote Tm[0] (item 0) above
             __syncthreads();
             // ---- Cholesky, right-looking, one barrier per column: the pivot
-            //      column m is used unscaled (products divided by the pivot) and
+            //      column m is used unscaled (products times the reciprocal of
+            //      the unrooted pivot K^(m)_mm) and
             //      scaled in place during column m+1's phase, when nothing reads
             //      it; u = L^{-1} Y is carried the same way.
             // The reciprocal of each pivot is formed once, by thread 0, which
