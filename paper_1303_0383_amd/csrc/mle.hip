@@ -149,14 +149,12 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             // ---- K and dK
             for (int e = tid; e < ntri; e += MT) {
                 const int a = row_of(e), b = e - half_prod(a, a + 1);
-                if (a == b) {
-                    Tm[e] = 1.0 + A.eta;
-                } else {
-                    const double d2 = sqdist_rows(xs, a, b, p);
-                    const double k = exp(-(d2 / theta));
-                    Tm[e] = k;
-                    Cd[sl(a, b)] = k * d2 / th2;
-                }
+                // the off-diagonal form is evaluated on the diagonal too and
+                // discarded there (no divergent branch around the exponential)
+                const double d2 = sqdist_rows(xs, a, b, p);
+                const double k = exp(-(d2 / theta));
+                Tm[e] = (a == b) ? 1.0 + A.eta : k;
+                if (a != b) Cd[sl(a, b)] = k * d2 / th2;
             }
             for (int a = tid; a < n; a += MT) u[a] = yv[a];
             if (tid == 0) red[0] = 1.0 / Tm[0];   // thread 0 wrote Tm[0] (item 0) above
@@ -219,8 +217,10 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 const int w1 = k + 1, qi = MT / w1, qc = MT - qi * w1;
                 int i = k + 1 + tid / w1, c = tid - (tid / w1) * w1;
                 for (; i < n;) {
-                    if (c == k) Tm[tri(i, k)] = -(ck[i] * rk);
-                    else Tm[tri(i, c)] -= ck[i] * (Tm[tri(k, c)] * rk);
+                    // both forms evaluated and one kept (no divergent branch)
+                    const int o = tri(i, c);
+                    const double upd = Tm[o] - ck[i] * (Tm[tri(k, c)] * rk);
+                    Tm[o] = (c == k) ? -(ck[i] * rk) : upd;
                     i += qi;
                     c += qc;
                     if (c >= w1) { c -= w1; ++i; }
