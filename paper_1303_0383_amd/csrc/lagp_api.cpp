@@ -506,6 +506,29 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
     return LAGP_OK;
 }
 
+// The likelihood kernel over a chunk's locations.  Its LDS is sized for the
+// largest design of a launch, so with uneven sizes it runs once per size
+// bucket (the bucket's part of the work list, LDS for the bucket's largest
+// design): small designs then share a CU instead of each taking the space of
+// the chunk's largest.
+static int mle_by_bucket(lagp::MleArgs m, const Chunk& c, const int32_t* order_dev, size_t max_lds, hipStream_t s)
+{
+    std::string err;
+    if (!order_dev || c.buckets.size() < 2) {
+        const int r = lagp::mle_run(m, max_lds, s, &err);
+        return r ? fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err) : 0;
+    }
+    for (const Bucket& b : c.buckets) {
+        if (b.count == 0) continue;
+        m.order = order_dev + c.t0 + b.first;
+        m.T = b.count;
+        m.nmax = b.nmax;
+        const int r = lagp::mle_run(m, max_lds, s, &err);
+        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    }
+    return 0;
+}
+
 // Enqueues the whole plan on stream s.  ws holds P.total bytes; order_dev is
 // the uploaded work list (uneven plans); n_per / ncand_per are device arrays.
 int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_dev, const int32_t* n_per,
@@ -617,8 +640,7 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
             m.maxit = P.mle.maxit;
             m.tol = P.mle.tol;
             m.theta_out = th1;
-            r = lagp::mle_run(m, d->max_lds, s, &err);
-            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+            if ((r = mle_by_bucket(m, c, order_dev, d->max_lds, s))) return r;
             if ((r = mark(LAGP_PHASE_MLE, 0))) return r;
             S.theta_per = th1;
             S.sel = L.sel;
@@ -630,8 +652,7 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
             m.sel_stride = L.sel_stride;
             m.theta0_per = th1;
             m.theta_out = th2;
-            r = lagp::mle_run(m, d->max_lds, s, &err);
-            if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+            if ((r = mle_by_bucket(m, c, order_dev, d->max_lds, s))) return r;
             if ((r = mark(LAGP_PHASE_MLE, 0))) return r;
             r = lagp::predict_run(d->dev, xx, c.T, L.sel, L.sel_stride, L.n_per, c.nmax, P.prm.d, th2, P.prm.g, L.mean,
                                   L.s2, L.df, L.var, L.status, d->max_lds, s, &err);

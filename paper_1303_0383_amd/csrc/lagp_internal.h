@@ -9,8 +9,6 @@
 
 namespace lagp {
 
-// Device-resident design: coordinate-major copy for streaming scans and a
-// row-major copy for gathers of single rows.
 // Raise a kernel's dynamic-LDS limit to what the device allows next to the
 // kernel's static LDS.  The limit is the device's rather than one launch's, so
 // that every launch of the kernel (eager or in a captured graph) fits.
@@ -23,6 +21,9 @@ inline bool set_lds_limit(const void* kernel, size_t max_lds)
                                (int)(max_lds - fa.sharedSizeBytes)) == hipSuccess;
 }
 
+// Device-resident design: row-major coordinates (read a row at a time by the
+// kNN scans and gathered by the other kernels), responses, and a strided
+// row sample for the kNN's radius estimate.
 struct DeviceDesign {
     const double* Xaos = nullptr;  // N x p
     const double* y = nullptr;     // N
@@ -141,19 +142,22 @@ struct MleArgs {
     const double* y = nullptr;
     int p = 0;
     int64_t N = 0;
-    int64_t T = 0;
-    const int32_t* sel = nullptr;   // T x sel_stride local design indices
+    int64_t T = 0;                  // locations this launch processes (the grid)
+    // nullable: the locations to process, T entries indexing the per-location
+    // arrays below (else locations 0 .. T-1)
+    const int32_t* order = nullptr;
+    const int32_t* sel = nullptr;   // local design indices, sel_stride per location
     int64_t sel_stride = 0;
     const int32_t* n_per = nullptr; // nullable: per-location design size
     int n = 0;                      // uniform design size
-    int nmax = 0;                   // largest design size (sizes LDS)
+    int nmax = 0;                   // largest design size of the processed locations (sizes LDS)
     const double* theta0_per = nullptr;   // nullable: per-location starting lengthscale
     double theta0 = 1.0;
     double eta = 0.0;
     double tmin = 0.0, tmax = 0.0;  // search interval
     int maxit = 0;
     double tol = 0.0;
-    double* theta_out = nullptr;    // T: the estimate (NaN where the design failed)
+    double* theta_out = nullptr;    // per location: the estimate (NaN where the design failed)
     int32_t* iters = nullptr;       // nullable: Newton iterates taken
     int8_t* status = nullptr;       // nullable: 0 OK, 1 failed
 };

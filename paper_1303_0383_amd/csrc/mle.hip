@@ -105,8 +105,8 @@ template <int MT>
 __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
 {
     extern __shared__ double sm[];
-    const int64_t t = blockIdx.x;
-    if (t >= A.T) return;
+    if ((int64_t)blockIdx.x >= A.T) return;
+    const int64_t t = A.order ? (int64_t)A.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int tid = threadIdx.x;
     const int p = A.p;
     const int n = A.n_per ? A.n_per[t] : A.n;
