@@ -181,19 +181,23 @@ def mspe_local(X, y, x, n0, n, M, d, g, L=None):
     return rc, sel, out, diag
 
 
-def batch(X, y, XX, n0, n, M, d, g, n_per=None, M_per=None, threads=0, L=None):
+def batch(X, y, XX, n0, n, M, d, g, n_per=None, M_per=None, threads=0, sel_stride=None, L=None):
     """All locations, OpenMP over locations.
 
-    Returns (status[T], sel[T, nmax], out[T, 5])."""
+    Returns (status[T], sel[T, sel_stride], out[T, 5]); sel_stride defaults to
+    the largest design size and entries past a location's n stay -1."""
     X = _f64(X); y = _f64(y); XX = _f64(XX)
     T = XX.shape[0]
     npe = None if n_per is None else _i32(n_per)
     mpe = None if M_per is None else _i32(M_per)
     nmax = int(npe.max()) if (npe is not None and T) else n
-    sel = np.full((T, nmax), -1, np.int32)
+    stride = nmax if sel_stride is None else int(sel_stride)
+    if stride < nmax:
+        raise ValueError("sel_stride below the largest design size")
+    sel = np.full((T, stride), -1, np.int32)
     out = np.empty((T, 5)); st = np.empty(T, np.int32)
     rc = (L or lib()).lagp_oracle_batch(_ptr(X), _ptr(y), X.shape[0], X.shape[1], _ptr(XX), T, n0, n, M,
-                                 _ptr(npe), _ptr(mpe), d, g, _ptr(sel), nmax, _ptr(out), _ptr(st),
+                                 _ptr(npe), _ptr(mpe), d, g, _ptr(sel), stride, _ptr(out), _ptr(st),
                                  int(threads))
     if rc < 0:
         raise ValueError(f"oracle batch failed: {rc}")

@@ -271,6 +271,57 @@ def pin_variance_nonnegative(L=None):
     assert np.allclose(out[:, 2], out[:, 1] * w.n / (w.n - 2), rtol=1e-15)
 
 
+def pin_alc_brute_dense(L=None):
+    """The oracle's brute-force mode, v_j(x) - v_{j+1}(x|c) from two fresh
+    factorisations, against the same difference by dense NumPy solves; an
+    augmented matrix that is singular (a candidate duplicating a design
+    point with no nugget) scores NaN."""
+    for (seed, p, theta, eta) in ((3, 2, 0.5, 1e-4), (4, 8, 1.0, 1e-4)):
+        X, y, x = small_problem(seed, N=60, p=p, lo=0.0 if p > 2 else -2.0, hi=1.0 if p > 2 else 2.0)
+        C, _ = oracle.knn(X, x, 30)
+        D, cand = C[:6], C[6:]
+        a = oracle.alc_brute(X, x, D, cand, theta, eta, L=L)
+        v0 = var_np(X[D], x, theta, eta)
+        dense = np.array([v0 - var_np(X[np.append(D, c)], x, theta, eta) for c in cand])
+        scale = max(np.abs(dense).max(), 1e-300)
+        assert np.max(np.abs(a - dense)) <= 1e-9 * scale, (seed, np.max(np.abs(a - dense)) / scale)
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 0.0], [0.5, 0.5]])
+    a = oracle.alc_brute(X, np.array([0.2, 0.1]), np.array([0, 1]), np.array([2, 3]), 0.5, 0.0, L=L)
+    assert np.isnan(a[0]) and np.isfinite(a[1]) and a[1] > 0
+
+
+def pin_batch_matches_local(L=None):
+    """The batch over locations (Section 4.1) writes, for every location, what
+    a single-location call gives: per-location n and N' override the uniform
+    values, rows sit at the caller's stride, entries past a location's n are
+    left alone, and the thread count changes nothing."""
+    X, y, _ = small_problem(29, N=140)
+    r = np.random.default_rng(30)
+    T = 9
+    XX = r.uniform(-1.8, 1.8, (T, 2))
+    n_per = r.integers(5, 19, T).astype(np.int32)
+    M_per = r.integers(20, 90, T).astype(np.int32)
+    n0, d, g = 4, 0.5, 1e-5
+    stride = int(n_per.max()) + 3
+    st, sel, out = oracle.batch(X, y, XX, n0, 12, 60, d, g, n_per=n_per, M_per=M_per, threads=3,
+                                sel_stride=stride, L=L)
+    assert sel.shape == (T, stride)
+    for t in range(T):
+        rc, s1, o1, _ = oracle.local(X, y, XX[t], n0, int(n_per[t]), int(M_per[t]), d, g, L=L)
+        assert st[t] == rc == 0
+        assert np.array_equal(sel[t, :n_per[t]], s1), t
+        assert np.all(sel[t, n_per[t]:] == -1), t
+        assert np.array_equal(out[t], o1), t
+    st1, sel1, out1 = oracle.batch(X, y, XX, n0, 12, 60, d, g, n_per=n_per, M_per=M_per, threads=1,
+                                   sel_stride=stride, L=L)
+    assert np.array_equal(sel1, sel) and np.array_equal(out1, out)
+    # uniform sizes: every location uses the call's n and N'
+    st2, sel2, out2 = oracle.batch(X, y, XX[:3], n0, 10, 50, d, g, L=L)
+    for t in range(3):
+        rc, s1, o1, _ = oracle.local(X, y, XX[t], n0, 10, 50, d, g, L=L)
+        assert np.array_equal(sel2[t], s1) and np.array_equal(out2[t], o1)
+
+
 def pin_design_ignores_y(L=None):
     X, y, x = small_problem(24, N=150)
     r1 = oracle.local(X, y, x, 4, 20, 100, 0.5, 1e-5, L=L)
@@ -318,7 +369,7 @@ def pin_replay_follows(L=None):
 PINS = [pin_knn_golden, pin_knn_nearest_set, pin_alc_three_forms, pin_alc_closed_form_j1,
         pin_symmetric_tie_golden, pin_greedy_is_brute_argmax, pin_bounds_along_path,
         pin_pie_and_updates, pin_full_gp, pin_nn_kriging, pin_interpolation,
-        pin_variance_nonnegative, pin_design_ignores_y, pin_permutation_invariance,
+        pin_variance_nonnegative, pin_alc_brute_dense, pin_batch_matches_local, pin_design_ignores_y, pin_permutation_invariance,
         pin_rotation_invariance, pin_replay_follows]
 
 
@@ -365,6 +416,12 @@ MUTATIONS = [
     ("predictive variance ignores the nugget", r"double vx = \(1\.0 \+ eta\) - dot\(wx, wx, n\);",
      "double vx = 1.0 - dot(wx, wx, n);"),
     ("mean uses the wrong vector", r"double mean = dot\(wx, u, n\);", "double mean = dot(wx, yd, n);"),
+    ("brute form appends the first candidate for every candidate", r"D1\[j\] = cand\[ci\];", "D1[j] = cand[0];"),
+    ("brute form reverses the difference", r"alc\[ci\] = v0 - v1;", "alc[ci] = v1 - v0;"),
+    ("batch ignores the per-location design size", r"int32_t nt = n_per \? n_per\[t\] : n;", "int32_t nt = n;"),
+    ("batch ignores the per-location candidate count", r"int64_t Mt = M_per \? M_per\[t\] : M;", "int64_t Mt = M;"),
+    ("batch rows at the design size instead of the stride", r"sel \+ \(size_t\)t \* sel_stride",
+     "sel + (size_t)t * nt"),
 ]
 
 
