@@ -59,7 +59,9 @@ typedef enum {
 
 /* Per-location status codes written to the optional `status` output. */
 enum { LAGP_LOC_OK = 0, LAGP_LOC_NOTPD = 1, LAGP_LOC_NOTCAND = 2 /* a saved starting-design index is not
-                                                                     among the location's candidates, or repeats */ };
+                                                                     among the location's candidates, or repeats */,
+       LAGP_LOC_NOCAND = 3 /* the candidate set could not be formed (a kNN consistency check failed; calls
+                              that wait on the host return an error instead) */ };
 
 /* Precision of the ALC scoring contraction.  The variance v_j(c), covariance
  * cov_j(x,c), the factor update and the final prediction are FP64 in every

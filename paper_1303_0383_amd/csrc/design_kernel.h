@@ -327,7 +327,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     (void)xsl;
 
     for (;;) {
-        if (tid == 0) ctl[0] = (int)atomicAdd(A.counter, 1u);
+        if (tid == 0) {
+            ctl[0] = (int)atomicAdd(A.counter, 1u);
+            ctl[3] = 0;   // set when some candidate entry is unset
+        }
         __syncthreads();
         const int64_t w = ctl[0];
         if (w >= (A.count ? (int64_t)*A.count : A.T)) break;
@@ -379,7 +382,9 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         for (int k = 0; k < CPT; ++k) {
             const int slot = tid + k * DT;
             if (slot < M) {
-                const int c = cand[slot];
+                const int c0 = cand[slot];
+                if (c0 < 0) ctl[3] = 1;
+                const int c = c0 < 0 ? 0 : c0;
                 ci[k] = c;
                 if (CL && ylds) Xc[(int64_t)p * Mpad + slot] = A.y[c];
                 const double* xc = A.Xaos + (int64_t)c * p;
@@ -452,11 +457,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             }
         }
         __syncthreads();
+        const int nocand = ctl[3];   // a candidate entry the kNN marked as unset (-1)
 
         // ---- greedy steps
         const int badstart = A.start ? ctl[2] : 0;
         int s_next = -1;
-        int notpd = (theta_ok && !badstart) ? 0 : 1;
+        int notpd = (theta_ok && !badstart && !nocand) ? 0 : 1;
         int nuse = n;   // design size reached (the stopping rule may end the search early)
         for (int i = 0; i < n && !notpd; ++i) {
             const int s = (i < n0) ? forced[i] : s_next;
@@ -784,7 +790,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             A.s2[t] = s2v;
             if (A.var) A.var[t] = var;
             if (A.df) A.df[t] = nuse;
-            if (A.status) A.status[t] = badstart ? 2 : notpd ? 1 : 0;
+            if (A.status) A.status[t] = nocand ? 3 : badstart ? 2 : notpd ? 1 : 0;
         }
         // the mixed mode's FP64 prediction reads the design size reached
         if (MIX && tid == 0 && A.vratio > 0.0 && A.df) A.df[t] = nuse;
@@ -802,7 +808,7 @@ static int launch_design(const DesignArgs* a, const DesignPlan& plan, hipStream_
     if (!a) {
         // Plans of one variant may differ in LDS size and a captured graph may
         // launch any of them: the limit is the device's.
-        if (!set_lds_limit((const void*)kern, plan.lds_limit)) {
+        if (!set_lds_limit((const void*)kern, plan.lds_limit, plan.lds_bytes)) {
             *err = "cannot reserve LDS for the design kernel";
             return -2;
         }

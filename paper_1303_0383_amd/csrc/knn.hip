@@ -496,9 +496,11 @@ knn_finalize_kernel(int64_t T, int32_t M_all, const int32_t* __restrict__ M_per,
     const uint32_t nb = counts[2 * t], nk = counts[2 * t + 1];
     const int tid = threadIdx.x;
     if (!s.settled || nb != s.below || nk != s.bucket || nb + nk < (uint32_t)M || nk > (uint32_t)bucket_max) {
-        // Cannot happen for finite inputs; keep the row's indices valid and report.
+        // Cannot happen for finite inputs.  Mark the row (-1 entries: the
+        // design kernel then fails the location with LAGP_LOC_NOCAND) and
+        // report through the flag, which calls that wait on the host read.
         int32_t* row = idx + t * idx_stride;
-        for (int e = tid; e < M; e += KNN_THREADS) row[e] = 0;
+        for (int e = tid; e < M; e += KNN_THREADS) row[e] = -1;
         if (tid == 0) atomicAdd(bad, 1);
         return;
     }

@@ -284,8 +284,10 @@ int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int3
 
 // Checks parameters and per-location sizes (host arrays, nullable) and builds the plan.
 int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
-               bool have_sel, bool have_status, Plan* P)
+               bool have_sel, bool have_status, Plan* P, int64_t chunk)
 {
+    if (chunk < 1) return fail(LAGP_E_INVAL, "chunk must be >= 1");
+    P->chunk = chunk;
     const int64_t N = d->dev.N;
     if (!(prm->d > 0.0) || !isfinite(prm->d)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
     if (!(prm->g >= 0.0) || !isfinite(prm->g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
@@ -323,13 +325,13 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
     P->Mmax = Mmax;
     P->own_sel = P->mix && !have_sel;
     P->own_status = P->mix && !have_status;
-    const int64_t tc_max = std::min(kChunk, std::max<int64_t>(T, 1));
+    const int64_t tc_max = std::min(chunk, std::max<int64_t>(T, 1));
     size_t design_b = 0;
     if (P->uneven) P->order.resize(T);
-    for (int64_t t0 = 0; t0 < T; t0 += kChunk) {
+    for (int64_t t0 = 0; t0 < T; t0 += chunk) {
         Chunk c;
         c.t0 = t0;
-        c.T = std::min(kChunk, T - t0);
+        c.T = std::min(chunk, T - t0);
         c.nmax = 0;
         c.Mmax = 0;
         if (!P->uneven) {
@@ -446,7 +448,7 @@ int plan_alc2(const lagp_design* d, const lagp_mle_params* mle, bool have_sel, P
     if (lagp::predict_lds_bytes(P->nmax) > d->max_lds) return fail(LAGP_E_INVAL, "n too large for the prediction kernel");
     P->alc2 = true;
     P->mle = *mle;
-    const int64_t tc_max = std::min(kChunk, std::max<int64_t>(P->T, 1));
+    const int64_t tc_max = std::min(P->chunk, std::max<int64_t>(P->T, 1));
     if (!have_sel && !P->own_sel) {
         P->own_sel = true;
         P->total -= P->sel_b;
@@ -546,7 +548,7 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
     uint32_t* redo_count = (uint32_t*)(q + (P.redo_b ? P.redo_b - 256 : 0));
     q += P.redo_b;
     int32_t* sel1_ws = (int32_t*)q;    q += P.sel1_b;
-    const int64_t tc_max = std::min(kChunk, std::max<int64_t>(P.T, 1));
+    const int64_t tc_max = std::min(P.chunk, std::max<int64_t>(P.T, 1));
     const size_t vb = lagp::align256((size_t)tc_max * sizeof(double));
     double* st_mean = (double*)q;
     double* st_s2 = (double*)(q + vb);

@@ -12,11 +12,15 @@ namespace lagp {
 // Raise a kernel's dynamic-LDS limit to what the device allows next to the
 // kernel's static LDS.  The limit is the device's rather than one launch's, so
 // that every launch of the kernel (eager or in a captured graph) fits.
-inline bool set_lds_limit(const void* kernel, size_t max_lds)
+// With dyn_bytes > 0 it also checks that a launch with that much dynamic
+// LDS fits next to the static part (a launch that does not fit aborts the
+// queue).
+inline bool set_lds_limit(const void* kernel, size_t max_lds, size_t dyn_bytes = 0)
 {
     hipFuncAttributes fa;
     if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return false;
     if (fa.sharedSizeBytes >= max_lds) return false;
+    if (fa.sharedSizeBytes + dyn_bytes > max_lds) return false;
     return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(max_lds - fa.sharedSizeBytes)) == hipSuccess;
 }

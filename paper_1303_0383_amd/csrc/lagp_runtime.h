@@ -59,6 +59,7 @@ struct Chunk {
 struct Plan {
     lagp_params prm{};
     int64_t T = 0;
+    int64_t chunk = kChunk;       // locations per launch sequence
     int32_t nmax = 0, Mmax = 0;
     int32_t nmin = 0;             // smallest design size
     bool uneven = false, mix = false, own_sel = false, own_status = false;
@@ -95,8 +96,9 @@ struct Outputs {
 
 // Checks parameters and per-location sizes (host arrays, nullable) and builds
 // the plan for T locations.
+// `chunk` bounds the locations per launch sequence (and so the workspace).
 int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
-               bool have_sel, bool have_status, Plan* P);
+               bool have_sel, bool have_status, Plan* P, int64_t chunk = kChunk);
 // Turns a plan into the two-stage scheme: checks the search controls and
 // n >= 2, and adds the stage workspace.  have_sel: the caller passes sel.
 int plan_alc2(const lagp_design* d, const lagp_mle_params* mle, bool have_sel, Plan* P);
