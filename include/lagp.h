@@ -327,6 +327,30 @@ void lagp_server_destroy(lagp_server *server);
 /* Seconds on the steady (monotonic) clock the server's timestamps use. */
 double lagp_monotonic_seconds(void);
 
+/* ---- An entry point that allocates nothing.
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lagp_predict with uniform sizes (params->n, params->ncand for every
+ * location) whose workspace is a fixed device array of
+ * LAGP_NOALLOC_SCRATCH_BYTES inside the library instead of memory allocated
+ * on the design.  Each device holds its own copy of the array from the first
+ * call there until the process ends.  Locations run in chunks small enough
+ * for a chunk's workspace to fit the array; a configuration whose single
+ * location does not fit returns LAGP_E_BUDGET.  Arguments, outputs and
+ * results are those of lagp_predict (device pointers; params->flags must be
+ * 0); the kNN runs its fixed pass budget without host waits, and a location
+ * whose candidate set fails the kNN's consistency check gets status
+ * LAGP_LOC_NOCAND.  Every call on a device shares that device's array: calls
+ * that overlap on one device (two host threads, two streams) race, so
+ * serialise them.  No memory is allocated or freed by this call. */
+#define LAGP_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int lagp_predict_noalloc(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
+                         double *mean, double *s2, int32_t *df, double *var, int32_t *sel, int64_t sel_stride,
+                         int8_t *status, void *stream);
+/* The size of that array in bytes (LAGP_NOALLOC_SCRATCH_BYTES). */
+size_t lagp_noalloc_scratch_bytes(void);
+
 /* Device bytes of workspace lagp_predict needs for a batch of T locations
  * with the given maxima (for admission control by callers). */
 int lagp_workspace_bytes(const lagp_design *design, int64_t T, int32_t nmax, int32_t ncand_max,

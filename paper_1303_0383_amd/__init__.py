@@ -70,6 +70,9 @@ _lib.lagp_mle.argtypes = [_P, C.c_int64, _P, C.c_int64, _P, C.c_int32, _P, C.c_d
                          C.POINTER(lagp_mle_params), _P, _P, _P, _P]
 _lib.lagp_predict_designs.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int32, C.c_double, _P, C.c_double,
                                       _P, _P, _P, _P, _P, _P]
+_lib.lagp_predict_noalloc.argtypes = [_P, _P, C.c_int64, C.POINTER(lagp_params), _P, _P, _P, _P, _P, C.c_int64,
+                                      _P, _P]
+_lib.lagp_noalloc_scratch_bytes.restype = C.c_size_t
 _lib.lagp_workspace_bytes.argtypes = [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
 _lib.lagp_timing_enable.argtypes = [_P, C.c_int]
 _lib.lagp_phase_times.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -93,7 +96,7 @@ for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_byt
            "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
            "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant",
            "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats", "lagp_predict_theta",
-           "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex", "lagp_predict_mspe"):
+           "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex", "lagp_predict_mspe", "lagp_predict_noalloc"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -172,6 +175,16 @@ def lagp_predict(design, XX, T: int, params: lagp_params, n_per, ncand_per, mean
     _check(_lib.lagp_predict(design, _ptr(XX), T, C.byref(params), _ptr(n_per), _ptr(ncand_per), _ptr(mean),
                              _ptr(s2), _ptr(df), _ptr(var), _ptr(sel), sel_stride, _ptr(status),
                              _stream(stream)))
+
+
+def lagp_predict_noalloc(design, XX, T: int, params: lagp_params, mean, s2, df, var, sel, sel_stride: int, status,
+                         stream=None) -> None:
+    _check(_lib.lagp_predict_noalloc(design, _ptr(XX), T, C.byref(params), _ptr(mean), _ptr(s2), _ptr(df), _ptr(var),
+                                     _ptr(sel), sel_stride, _ptr(status), _stream(stream)))
+
+
+def lagp_noalloc_scratch_bytes() -> int:
+    return int(_lib.lagp_noalloc_scratch_bytes())
 
 
 def lagp_predict_ex(design, XX, T: int, params: lagp_params, opts, n_per, ncand_per, mean, s2, df, var, sel,
