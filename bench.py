@@ -48,6 +48,91 @@ def design_flops(n: int, M: int, p: int, n0: int) -> int:
     return f
 
 
+def design_alg_bytes(n: int, M: int, p: int) -> int:
+    """Algorithmic HBM bytes of the greedy-design kernel for one location: the
+    location (8p), its candidate list (4M), the candidates' coordinates and
+    responses gathered from the design (8M(p+1)), and the outputs (mean, s2,
+    var, df and n design indices: 28 + 4n).  The whitened tile and every
+    other intermediate could stay on chip, so they are not counted."""
+    return 8 * p + 4 * M + 8 * M * (p + 1) + 28 + 4 * n
+
+
+def knn_alg_flops(T: int, N: int, p: int) -> int:
+    """One squared distance (3p flops: p subtractions, p squares, p - 1 adds
+    and the comparison's share rounded to p) per location-design pair."""
+    return T * N * 3 * p
+
+
+def mle_iterate_flops(n: int) -> float:
+    """FP64 flops of one Newton iterate of the likelihood kernel: Cholesky,
+    in-place inversion, the K^{-1}-entry traces, the dK L^{-T} panels and the
+    L^{-1} H products, about 4/3 n^3 multiply-adds."""
+    return 8.0 / 3.0 * n ** 3
+
+
+def kernel_source_hash() -> str:
+    """Hash of the design kernel's sources: counter files record the hash they
+    were taken with, and a counter file taken with other sources is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("design_kernel.h", "design.hip"):
+        with open(os.path.join(ROOT, "paper_1303_0383_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it is missing or was taken with other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha16") != kernel_source_hash():
+        return None
+    return float(vals["bytes_per_launch"]) if "bytes_per_launch" in vals else None
+
+
+def roofline_entry(kernel: str, flops: float, alg_bytes: float, traffic, avg_s: float) -> dict:
+    """The kernel's bound is the larger of its FP64 flop fraction and its
+    measured-traffic fraction of HBM peak; `achieved` and `frac` are against
+    that roof (algorithmic bytes for the memory roof).  All three fractions
+    are reported."""
+    flop_rate = flops / avg_s / 1e12
+    flop_frac = flop_rate / FP64_PEAK_TFLOPS
+    alg_rate = alg_bytes / avg_s / 1e9
+    e = {"kernel": kernel}
+    traffic_frac = None
+    if traffic:
+        traffic_frac = traffic / avg_s / 1e9 / HBM_PEAK_GBS
+    if traffic_frac is not None and traffic_frac > flop_frac:
+        e.update(bound="hbm", achieved=round(alg_rate, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=round(alg_rate / HBM_PEAK_GBS, 5))
+    else:
+        e.update(bound="alu", achieved=round(flop_rate, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                 frac=round(flop_frac, 4))
+    e.update(traffic=traffic, avg_launch_ms=round(avg_s * 1e3, 3),
+             flop_frac=round(flop_frac, 4), flops_per_launch=flops,
+             alg_bytes_per_launch=alg_bytes, alg_byte_frac=round(alg_rate / HBM_PEAK_GBS, 5),
+             traffic_frac_of_hbm_peak=None if traffic_frac is None else round(traffic_frac, 4),
+             traffic_over_alg_bytes=None if not traffic else round(traffic / alg_bytes, 1))
+    return e
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def design_exps(n: int, M: int) -> int:
     return M + sum(M - i - 1 for i in range(n - 1))
 
@@ -228,22 +313,26 @@ def main() -> int:
     launches_per_step = max(1, launches // args.steps)
     per_launch_flops = flops / launches_per_step
     avg_launch_s = des_ms / max(launches, 1) / 1e3
-    achieved = per_launch_flops / avg_launch_s / 1e12
-    roofline = {"kernel": "mspe_kernel" if mspe else "design_kernel", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": launches_per_step,
-                "flops_per_launch": per_launch_flops, "exps_per_launch": exps / launches_per_step,
-                "exp_rate_G_per_s": round(exps / launches_per_step / avg_launch_s / 1e9, 2)}
-    traffic_file = os.path.join(ROOT, "profiles", f"{roofline['kernel']}_{args.workload}_traffic.txt")
-    if os.path.exists(traffic_file) and args.precision == "fp64":
-        for line in open(traffic_file):
-            if line.startswith("bytes_per_launch:"):
-                roofline["traffic"] = float(line.split(":")[1])
-        if roofline["traffic"]:
-            # measured HBM traffic per launch over this run's launch time: the
-            # rate at which the kernel streams its tile
-            roofline["traffic_rate_TBps"] = round(roofline["traffic"] / avg_launch_s / 1e12, 3)
-            roofline["traffic_frac_of_hbm_peak"] = round(roofline["traffic"] / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    if w.n_per is not None:
+        alg_bytes = sum(design_alg_bytes(int(a), int(b), w.p) for a, b in zip(w.n_per, w.ncand_per))
+    else:
+        alg_bytes = T * design_alg_bytes(w.n, w.ncand, w.p)
+    kname = "mspe_kernel" if mspe else "design_kernel"
+    # counter files hold the FP64 one-stage kernel's traffic for a workload
+    traffic = read_traffic(kname, args.workload) if (args.precision == "fp64" and not alc2) else None
+    roofline = roofline_entry(kname, per_launch_flops, passes * alg_bytes / launches_per_step, traffic, avg_launch_s)
+    roofline.update(launches_per_step=launches_per_step, exps_per_launch=exps / launches_per_step,
+                    exp_rate_G_per_s=round(exps / launches_per_step / avg_launch_s / 1e9, 2))
+    # Each kernel's fraction of its roof: the kNN (one distance per
+    # location-design pair, FP64 flops; its scans run about two full passes),
+    # the design kernel (above) and, in the two-stage scheme, the likelihood kernel.
+    kernels = {"design": {k: roofline[k] for k in ("bound", "frac", "flop_frac", "alg_byte_frac",
+                                                    "traffic_frac_of_hbm_peak")}}
+    knn_ms = phase["knn"] / args.steps
+    if knn_ms > 0:
+        kf = knn_alg_flops(T, w.N, w.p) / (knn_ms / 1e3) / 1e12
+        kernels["knn"] = {"bound": "alu", "ms_per_step": round(knn_ms, 3), "achieved_TFLOPs": round(kf, 3),
+                          "frac": round(kf / FP64_PEAK_TFLOPS, 4), "alg_flops": knn_alg_flops(T, w.N, w.p)}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "locations/s", "n_gpus": 1,
@@ -256,6 +345,7 @@ def main() -> int:
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),
         "roofline": roofline,
+        "kernels": kernels,
     }
 
     if alc2:
@@ -273,6 +363,14 @@ def main() -> int:
                          "iterates_from_theta1": round(float(it2.double().mean().item()), 3),
                          "location_iterates_per_step": n_it,
                          "ns_per_location_iterate": round(mle_ms * 1e6 / max(n_it, 1), 2)}
+        if mle_ms > 0:
+            # iterates by design size: the two passes' designs have the step's sizes
+            sizes = w.n_per if w.n_per is not None else np.full(T, w.n)
+            per_loc = (it1.cpu().numpy() + it2.cpu().numpy()).astype(np.float64)
+            mf = float(np.sum(per_loc * mle_iterate_flops(sizes.astype(np.float64))))
+            rate = mf / (mle_ms / 1e3) / 1e12
+            kernels["mle"] = {"bound": "alu", "ms_per_step": round(mle_ms, 3), "achieved_TFLOPs": round(rate, 3),
+                              "frac": round(rate / FP64_PEAK_TFLOPS, 4), "alg_flops": mf}
         del first
 
     res = {k: getattr(out, k).cpu().numpy() for k in ("mean", "s2", "df", "var", "sel", "status")}
@@ -384,9 +482,19 @@ def main() -> int:
                          M_per=sub.ncand_per, threads=threads)
         cpu_s = time.perf_counter() - tc
         result["cpu_baseline"] = {"value": round(len(idx) / cpu_s, 2), "unit": "locations/s", "cores": threads,
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model(),
                                   "sample": f"{len(idx)} seeded locations of the same workload, {cpu_s:.1f} s, "
                                             f"OpenMP over locations"}
+        if not (mspe or alc2):
+            # single-thread rate on a smaller sample of the same locations
+            k1 = max(4, len(idx) // (2 * max(threads, 1)))
+            sub1 = w.subset(idx[:k1])
+            tc = time.perf_counter()
+            oracle.batch(sub1.X, sub1.y, sub1.XX, sub1.n0, sub1.n, sub1.ncand, sub1.d, sub1.g, n_per=sub1.n_per,
+                         M_per=sub1.ncand_per, threads=1)
+            one_s = time.perf_counter() - tc
+            result["cpu_baseline"]["single_thread"] = {"value": round(k1 / one_s, 2), "unit": "locations/s",
+                                                       "sample": f"first {k1} locations of that sample, {one_s:.1f} s"}
     print(json.dumps(result), flush=True)
     return 0
 
@@ -474,11 +582,10 @@ def serve_bench(args, lagp, torch) -> int:
     knn_ms, des_ms = phase["knn"], phase["design"]
     lagp.lagp_timing_enable(D.handle, False)
     flops = sum(design_flops(int(a), int(b), 4, prm["n0"]) for a, b in zip(n_per, M_per))
-    achieved = flops / (des_ms / 1e3) / 1e12
-    roofline = {"kernel": "design_kernel", "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "avg_launch_ms": round(des_ms / max(launches, 1), 3), "launches_per_step": launches,
-                "flops_per_launch": flops / max(launches, 1), "knn_ms_per_burst": round(knn_ms, 3)}
+    alg = sum(design_alg_bytes(int(a), int(b), 4) for a, b in zip(n_per, M_per))
+    nl = max(launches, 1)
+    roofline = roofline_entry("design_kernel", flops / nl, alg / nl, None, des_ms / nl / 1e3)
+    roofline.update(launches_per_step=launches, knn_ms_per_burst=round(knn_ms, 3))
 
     result = {
         "metric": METRIC, "value": round(sat, 1), "unit": "locations/s", "n_gpus": 1, "steps": args.steps,
@@ -500,7 +607,7 @@ def serve_bench(args, lagp, torch) -> int:
                      n_per=n_per[idx], M_per=M_per[idx], threads=threads)
         cpu_s = time.perf_counter() - tc
         result["cpu_baseline"] = {"value": round(k / cpu_s, 2), "unit": "locations/s", "cores": threads,
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model(),
                                   "sample": f"{k} seeded locations of the serving burst, {cpu_s:.1f} s, "
                                             f"OpenMP over locations"}
     print(json.dumps(result), flush=True)

@@ -55,11 +55,9 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     const size_t crow_bytes = (size_t)Mpad * sizeof(double);                          // coordinate row
     const size_t avail = max_lds - fixed;
     // Option A: coordinates in LDS.  Option B: coordinates in global memory.
-    // Cost: bytes read from global memory per location.
-    // Option A keeps the coordinates and the responses in LDS (one step needs
-    // one response, read there); option B keeps the coordinates in the
-    // global slab and reads the chosen response from the design.
-    const int pcA = p + 1, pc = p;
+    // Cost: bytes read from global memory per location.  Either way a step
+    // reads its one response from the design (LDS is worth more as tile rows).
+    const int pcA = p, pc = p;
     // Trimmed variant when some location leaves a whole slot column empty.
     const bool trim = cpt > 1 && Mmin <= (cpt - 1) * dt;
     const int rregA = rreg_for(dt, cpt, true, mix, trim), rregB = rreg_for(dt, cpt, false, mix, trim);
@@ -86,7 +84,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     plan->rglob = (cl ? remA : remB) - plan->rlds;
     plan->coords_lds = cl;
     plan->lds_bytes = fixed + (cl ? pcA * crow_bytes : 0) + (size_t)plan->rlds * row_bytes;
-    plan->y_lds = cl;
+    plan->y_lds = false;
     plan->scratch_per_block = align256((cl ? 0 : pc * crow_bytes) + (size_t)plan->rglob * row_bytes);
     plan->blocks = num_cu;
     plan->counter_bytes = 256;

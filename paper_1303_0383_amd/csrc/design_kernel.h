@@ -40,6 +40,10 @@
 
 #include "lagp_internal.h"
 
+#ifndef LAGP_RING_DEPTH
+#define LAGP_RING_DEPTH 3
+#endif
+
 namespace lagp {
 
 
@@ -155,51 +159,50 @@ __device__ __forceinline__ double sqdist_lds(const double* __restrict__ a, const
 
 // Rows of the whitened tile kept in registers for a workgroup size, slot
 // count, coordinate placement, tile precision and trimming: the largest
-// multiple of 4 that compiles without scratch spills (measured for P = 8),
-// except where timing favoured a few more rows despite a small spill.
-// With 256 threads (one wave per SIMD) a lane can hold 512 registers, the
-// upper half as accumulation registers; with 512 threads a lane has 256.
+// multiple of 4 that compiles without scratch spills for P = 8 (a compile
+// sweep), capped at 64 (with one slot per thread LDS holds the rest).  With
+// 256 threads (one wave per SIMD) a lane can hold 512 registers, the upper
+// half as accumulation registers; with 512 threads a lane has 256.
 __host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = false, bool trim = false)
 {
     if (dt == 256) {
         if (!mix) {
             switch (cpt) {
-            case 1: return cl ? 88 : 80;
-            case 2: return (cl || trim) ? 44 : 40;
-            case 4: return (cl || trim) ? 20 : 16;
-            // 8 rows spill 64 bytes per lane here and are still faster than 4
-            // (222 against 230 ms on a 100k x 8 design, n = 50, N' = 2000)
-            default: return (cl && !trim) ? 8 : (cl || trim) ? 4 : 0;
+            case 1: return 64;
+            case 2: return 64;
+            case 4: return 40;
+            default: return 16;
             }
         }
         switch (cpt) {
-        case 1: return 128;
-        case 2: return (cl || trim) ? 96 : 88;
-        case 4: return (cl || trim) ? 44 : 36;
-        default: return (cl || trim) ? 16 : 8;
+        case 1: return 64;
+        case 2: return 64;
+        case 4: return 64;
+        default: return 36;
         }
     }
     if (!mix) {
         switch (cpt) {
-        case 1: return 24;
-        case 2: return 12;
-        case 4: return 4;
+        case 1: return 64;
+        case 2: return 32;
+        case 4: return cl ? 8 : 12;
         default: return 0;
         }
     }
     switch (cpt) {
     case 1: return 64;
-    case 2: return 28;
-    case 4: return trim ? 12 : 8;
-    default: return 0;
+    case 2: return cl ? 64 : 60;
+    case 4: return cl ? 20 : 24;
+    default: return cl ? 0 : 4;
     }
 }
 
-// Rows per prefetch block of the global part of the tile (two blocks are in
-// flight).
-__host__ __device__ constexpr int prefetch_rows(int cpt)
+// Global tile rows in the load ring per workgroup step (rows in flight + the
+// one being consumed): about four rows of a 256-thread workgroup in flight
+// cover the memory latency at full streaming rate.
+__host__ __device__ constexpr int ring_depth(int cpt, bool mix)
 {
-    return cpt >= 4 ? 2 : 8 / cpt;
+    return (cpt * (mix ? 4 : 8)) >= 64 ? LAGP_RING_DEPTH : 5;
 }
 
 // Combine (value, design index, slot) with a partner lane's triple.
@@ -282,6 +285,13 @@ __device__ __forceinline__ void ld4(const float* p, float* o)
 // MIX: the whitened tile stored and contracted in FP32 (ranking only), TRIM:
 // locations may leave whole slot columns empty (candidate sets well below
 // CPT * DT), whose global-memory traffic and exponentials are then skipped.
+//
+// Register economy decides how many tile rows stay on chip, so the step loop
+// keeps few values alive besides the tile: the exponentials of a step are
+// evaluated slot by slot (an empty asm with a memory clobber keeps the
+// compiler from hoisting every slot's coordinate loads at once), LDS rows are
+// consumed one at a time, and the global rows stream through a ring of three
+// row buffers (two rows in flight while one is consumed).
 template <int DT, int CPT, int RREG, int P, bool CL, bool MIX, bool TRIM>
 __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 {
@@ -302,12 +312,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     double* uu = smem + 2 * nmax;    // [nmax] L^{-1} Y
     double* xl = uu + nmax;          // [p]    predictive location
     double* xsl = xl + p;            // [p+1]  (spare)
-    double* misc = xsl + p + 1;      // [4]    v_s
+    double* misc = xsl + p + 1;      // [4]    v_s, v_j(x)
     double* redv = misc + 4;         // [2*DWAVES] per-wave best scores
     int* redi = (int*)(redv + 2 * DWAVES);  // [2*DWAVES] best design index
     int* reds = redi + 2 * DWAVES;          // [2*DWAVES] best slot
-    int* forced = reds + 2 * DWAVES;        // [nmax] slots of the nearest neighbours
-    int* ctl = forced + nmax;               // [4]  location
+    int* forced = reds + 2 * DWAVES;        // [nmax] slots of the starting design
+    int* ctl = forced + nmax;               // [4]  location, chosen index, bad start, unset candidate
     size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
     off = (off + 15) & ~(size_t)15;
     const int ylds = CL ? A.y_lds : 0;
@@ -321,6 +331,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     const int voff_c = tid * (int)sizeof(double);     // coordinate element of slot k = 0
     const int voff_w = tid * (int)sizeof(TW);         // tile-row element of slot k = 0
     const int wbase = CL ? 0 : p * Mpad * (int)sizeof(double);   // tile rows after the coordinates
+    const int rowb = Mpad * (int)sizeof(TW);                      // bytes per global tile row
     const int rlds = A.rlds;
     const int G0 = RREG + rlds;   // first global row
     for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = 0.0;
@@ -349,9 +360,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         // ignored) and their exponentials are skipped.
         const int kact = (M + DT - 1) / DT;
         const bool full = !TRIM || kact == CPT;
-        int koff[CPT];
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) koff[k] = (k < kact ? k : kact - 1) * DT;
         const int n0 = (A.start && A.start_n) ? A.start_n[t] : A.n0;
         const int32_t* cand = A.cand + t * A.cand_stride;
         for (int k = tid; k < p; k += DT) xl[k] = A.XX[t * p + k];
@@ -361,12 +369,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         if (A.sel)
             for (int i = tid; i < n; i += DT) A.sel[t * A.sel_stride + i] = -1;
         __syncthreads();
-        double xr[P > 0 ? P : 1];
-        if (P > 0) {
-#pragma unroll
-            for (int k = 0; k < (P > 0 ? P : 1); ++k) xr[k] = xl[k];
-        }
-        const double* xp = P > 0 ? xr : xl;
 
         // ---- gather candidates (coordinates and y into the coordinate block);
         //      K(x,c) and v_0(c) = 1 + g
@@ -393,24 +395,24 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     const double ck = xc[kk];
                     if (CL) Xc[(int64_t)kk * Mpad + slot] = ck;
                     else bstore(slab, voff_c, (kk * Mpad + k * DT) * (int)sizeof(double), ck);
-                    const double tt = xp[kk] - ck;
+                    const double tt = xl[kk] - ck;
                     sq += tt * tt;
                 }
                 d2[k] = sq;
                 cov[k] = exp(-div_by(sq, theta, rtheta));
-                v[k] = one_eta;
             } else {
                 ci[k] = 0x7fffffff;
                 if (CL && ylds) Xc[(int64_t)p * Mpad + slot] = 0.0;
                 d2[k] = INFINITY;
                 cov[k] = 0.0;
-                v[k] = one_eta;
                 chosen |= 1u << k;
                 for (int kk = 0; kk < p; ++kk) {
                     if (CL) Xc[(int64_t)kk * Mpad + slot] = 0.0;
                     else bstore(slab, voff_c, (kk * Mpad + k * DT) * (int)sizeof(double), 0.0);
                 }
             }
+            v[k] = one_eta;
+            asm volatile("" ::: "memory");
         }
 
         // ---- starting design: a saved design located among the candidates, or
@@ -464,9 +466,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         int s_next = -1;
         int notpd = (theta_ok && !badstart && !nocand) ? 0 : 1;
         int nuse = n;   // design size reached (the stopping rule may end the search early)
-        for (int i = 0; i < n && !notpd; ++i) {
+        // Full steps i = 0 .. n-2 append row i of W for every candidate and
+        // choose the next point; the last chosen point is appended after the
+        // loop (only its own column is needed there).
+        for (int i = 0; i < n - 1 && !notpd && nuse == n; ++i) {
             const int s = (i < n0) ? forced[i] : s_next;
-            if (s < 0 || s >= M) { notpd = 1; break; }
+            if (s < 0 || s >= M) { notpd = 1; continue; }
             const int s_lane = s % DT;
             const int s_k = s / DT;
             // Phase A (before the barrier): the owner publishes the register
@@ -488,29 +493,28 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             }
             for (int l = RREG + tid; l < i; l += DT)
                 ws[l] = (l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s];
-            double xs[P > 0 ? P : 1];
-            if (P > 0) {
-#pragma unroll
-                for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
-            }
             // one response per step: from LDS when it holds them, else from the design
             const double ys = (CL && ylds) ? Xc[(int64_t)p * Mpad + s] : A.y[cand[s]];
-            const double* xsp = P > 0 ? xs : xl;   // runtime dimension: read below from Xc
             double ax, acc[CPT];
             if (P > 0) {
-                ax = exp(-div_by(sqdist_lds<P>(xsp, xl, 1, p), theta, rtheta));
-                // K(s, c): coordinates from LDS, or from the slab.
-                auto sqd = [&](int k) {
-                    if constexpr (CL) return sqdist_lds<P>(xsp, Xc + tid + k * DT, Mpad, p);
-                    else return sqdist_slab<(P > 0 ? P : 1)>(xsp, slab, voff_c, k * DT * (int)sizeof(double),
-                                                             Mpad * (int)sizeof(double));
-                };
-                if (full) {
+                double xs[P > 0 ? P : 1];
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) acc[k] = exp(-div_by(sqd(k), theta, rtheta));
-                } else {
+                for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
+                ax = exp(-div_by(sqdist_lds<P>(xs, xl, 1, p), theta, rtheta));
+                // K(s, c) slot by slot: coordinates from LDS, or from the slab.
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) acc[k] = k < kact ? exp(-div_by(sqd(k), theta, rtheta)) : 0.0;
+                for (int k = 0; k < CPT; ++k) {
+                    double sq;
+                    if constexpr (CL) sq = sqdist_lds<P>(xs, Xc + tid + k * DT, Mpad, p);
+                    else sq = sqdist_slab<(P > 0 ? P : 1)>(xs, slab, voff_c, k * DT * (int)sizeof(double),
+                                                           Mpad * (int)sizeof(double));
+                    // A runtime branch per slot (kact == CPT for full
+                    // candidate sets) keeps the compiler from interleaving
+                    // the slots' exponentials, which would cost tile rows.
+                    double e = 0.0;
+                    if (k < kact) e = exp(-div_by(sq, theta, rtheta));
+                    acc[k] = e;
+                    asm volatile("" ::: "memory");
                 }
             } else {
                 double sqx = 0.0, sq[CPT];
@@ -528,66 +532,55 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 }
                 ax = exp(-div_by(sqx, theta, rtheta));
 #pragma unroll
-                for (int k = 0; k < CPT; ++k) acc[k] = exp(-div_by(sq[k], theta, rtheta));
+                for (int k = 0; k < CPT; ++k) {
+                    acc[k] = exp(-div_by(sq[k], theta, rtheta));
+                    asm volatile("" ::: "memory");
+                }
             }
-            (void)xsp;
 
-            // Prefetch the first global rows.
-            constexpr int U = prefetch_rows(CPT);
-            TW pre[U][CPT];
+            // The first global rows are requested before the barrier.
+            constexpr int DEPTH = ring_depth(CPT, MIX);
+            TW bq[DEPTH][CPT];
+            const int gcount = i > G0 ? i - G0 : 0;
+            // Row loads are issued unconditionally (no branch between a load
+            // and its use, so the compiler can count the loads in flight
+            // instead of draining them): a row not yet written, or past the
+            // slab, is read but never consumed (the descriptor returns zeros
+            // past the slab).
+            auto load_row = [&](int l, TW* b) {
+                const int rb = wbase + (l - G0) * rowb;
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    bload(slab, voff_w, rb + (full ? k * DT : (k < kact ? k : kact - 1) * DT) * (int)sizeof(TW), b[k]);
+            };
+            if (gcount > 0) {
+#pragma unroll
+                for (int q = 0; q + 1 < DEPTH; ++q) load_row(G0 + q, bq[q]);
+            }
             float dot[CPT], dotx = 0.0f;   // FP32 contraction (MIX)
 #pragma unroll
             for (int k = 0; k < CPT; ++k) dot[k] = 0.0f;
-            const int gcount = i > G0 ? i - G0 : 0;
-            if (gcount > 0) {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (u < gcount) {
-                        const int rb = wbase + u * Mpad * (int)sizeof(TW);
-                        if (full) {
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) bload(slab, voff_w, rb + k * DT * (int)sizeof(TW), pre[u][k]);
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) bload(slab, voff_w, rb + koff[k] * (int)sizeof(TW), pre[u][k]);
-                        }
-                    }
-            }
             __syncthreads();   // B1: column of s and v(s) published
 
             const double vs = misc[0];
-            if (!(vs > 0.0)) { notpd = 1; break; }
+            if (!(vs > 0.0)) { notpd = 1; continue; }
             const double delta = sqrt(vs);
             const double rdelta = 1.0 / delta;
             double ay = ys;
-            if (i == n - 1) {
-                for (int l = 0; l < i; ++l) {
-                    const double w = ws[l];
-                    ax -= w * (double)wx[l];
-                    ay -= w * uu[l];
-                }
-                if (tid == 0) {
-                    wx[i] = div_by(ax, delta, rdelta);
-                    uu[i] = div_by(ay, delta, rdelta);
-                    if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
-                }
-                break;
-            }
-
             // Row i of W for every live candidate: acc = K(s,c) - sum_l ws[l] W[l][c].
             // Register rows, four per block; rows >= i within a block are zero.
 #pragma unroll
             for (int l0 = 0; l0 < (RREG > 0 ? RREG : 0); l0 += 4) {
                 if (l0 < i) {
-                    TW w[4], xv[4];
-                    ld4(ws + l0, w);
+                    TW wv[4], xv[4];
+                    ld4(ws + l0, wv);
                     ld4(wx + l0, xv);
                     if constexpr (MIX) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                            for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(w[r], Wr[l0 + r][k], dot[k]);
-                            dotx = __builtin_fmaf(w[r], xv[r], dotx);
+                            for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wv[r], Wr[l0 + r][k], dot[k]);
+                            dotx = __builtin_fmaf(wv[r], xv[r], dotx);
                         }
                     } else {
                         double uv[4];
@@ -595,98 +588,61 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                            for (int k = 0; k < CPT; ++k) acc[k] -= w[r] * Wr[l0 + r][k];
-                            ax -= w[r] * xv[r];
-                            ay -= w[r] * uv[r];
+                            for (int k = 0; k < CPT; ++k) acc[k] -= wv[r] * Wr[l0 + r][k];
+                            ax -= wv[r] * xv[r];
+                            ay -= wv[r] * uv[r];
                         }
                     }
                 }
             }
+            // LDS rows [RREG, min(i, G0)), one at a time.
             {
-                // LDS rows [RREG, min(i, G0)), four per block.  A block may run
-                // past i (or past G0 into rows that are never written): the
-                // weight is zero there and the LDS rows hold finite values, so
-                // those terms subtract an exact 0.
                 const int le = i < G0 ? i : G0;
-                constexpr int QB = CPT >= 8 ? 1 : CPT == 4 ? 2 : 4;   // rows loaded ahead
-#pragma unroll 2
-                for (int l0 = RREG; l0 < le; l0 += 4) {
-                    TW w[4], xv[4];
-                    double uv[4];
-                    ld4(ws + l0, w);
-                    ld4(wx + l0, xv);
-                    if constexpr (!MIX) ld4(uu + l0, uv);
+                for (int l = RREG; l < le; ++l) {
+                    const TW wl = ws[l];
+                    const TW* row = Wl + (int64_t)(l - RREG) * Mpad + tid;
+                    if constexpr (MIX) {
 #pragma unroll
-                    for (int r0 = 0; r0 < 4; r0 += QB) {
-                        TW q[QB][CPT];
+                        for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wl, row[k * DT], dot[k]);
+                        dotx = __builtin_fmaf(wl, wx[l], dotx);
+                    } else {
 #pragma unroll
-                        for (int r = 0; r < QB; ++r) {
-                            const int lr = (l0 + r0 + r < G0) ? l0 + r0 + r : l0;   // stay inside the LDS tile
-                            const TW* row = Wl + (int64_t)(lr - RREG) * Mpad + tid;
-#pragma unroll
-                            for (int k = 0; k < CPT; ++k) q[r][k] = row[k * DT];
-                        }
-#pragma unroll
-                        for (int r = 0; r < QB; ++r) {
-                            const TW wr = (l0 + r0 + r < le) ? w[r0 + r] : (TW)0;
-                            if constexpr (MIX) {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wr, q[r][k], dot[k]);
-                                dotx = __builtin_fmaf(wr, xv[r0 + r], dotx);
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) acc[k] -= wr * q[r][k];
-                                ax -= wr * xv[r0 + r];
-                                ay -= wr * uv[r0 + r];
-                            }
-                        }
+                        for (int k = 0; k < CPT; ++k) acc[k] -= wl * row[k * DT];
+                        ax -= wl * wx[l];
+                        ay -= wl * uu[l];
                     }
                 }
             }
+            // Global rows through the ring: row l is consumed while rows
+            // l+1 .. l+DEPTH-1 are in flight.  Per-candidate order stays ascending.
             if (gcount > 0) {
-                // Global rows in blocks of U, the next block loaded before the
-                // current one is consumed.  Per-candidate order stays ascending.
+                auto consume = [&](int l, const TW* b) {
+                    const TW wl = ws[l];
+                    if constexpr (MIX) {
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wl, b[k], dot[k]);
+                        dotx = __builtin_fmaf(wl, wx[l], dotx);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) acc[k] -= wl * b[k];
+                        ax -= wl * wx[l];
+                        ay -= wl * uu[l];
+                    }
+                };
+                // Whole blocks of DEPTH rows with no exit inside a block, then
+                // the last rows, which are already in flight.
                 int l = G0;
-                while (l < i) {
-                    const int nb = (i - l) < U ? (i - l) : U;     // rows in pre[]
-                    const int l2 = l + nb;
-                    const int nb2 = (i - l2) < U ? (i - l2) : U;   // rows of the next block
-                    TW nxt[U][CPT];
+                for (int nb = gcount / DEPTH; nb > 0; --nb) {
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (u < nb2) {
-                            const int rb = wbase + (l2 + u - G0) * Mpad * (int)sizeof(TW);
-                            if (full) {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k)
-                                    bload(slab, voff_w, rb + k * DT * (int)sizeof(TW), nxt[u][k]);
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k)
-                                    bload(slab, voff_w, rb + koff[k] * (int)sizeof(TW), nxt[u][k]);
-                            }
-                        }
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (u < nb) {
-                            const TW w = ws[l + u];
-                            if constexpr (MIX) {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(w, pre[u][k], dot[k]);
-                                dotx = __builtin_fmaf(w, wx[l + u], dotx);
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < CPT; ++k) acc[k] -= w * pre[u][k];
-                                ax -= w * wx[l + u];
-                                ay -= w * uu[l + u];
-                            }
-                        }
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-#pragma unroll
-                        for (int k = 0; k < CPT; ++k) pre[u][k] = nxt[u][k];
-                    l = l2;
+                    for (int q = 0; q < DEPTH; ++q) {
+                        load_row(l + DEPTH - 1, bq[(q + DEPTH - 1) % DEPTH]);
+                        consume(l, bq[q]);
+                        ++l;
+                    }
                 }
+#pragma unroll
+                for (int q = 0; q + 1 < DEPTH; ++q)
+                    if (l + q < i) consume(l + q, bq[q]);
             }
             if constexpr (MIX) {
                 ax -= (double)dotx;
@@ -719,15 +675,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
             } else {
-                const int rb = wbase + (i - G0) * Mpad * (int)sizeof(TW);
-                if (full) {
+                const int rb = wbase + (i - G0) * rowb;
 #pragma unroll
-                    for (int k = 0; k < CPT; ++k) bstore(slab, voff_w, rb + k * DT * (int)sizeof(TW), (TW)r[k]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < CPT; ++k)
-                        if (k < kact) bstore(slab, voff_w, rb + k * DT * (int)sizeof(TW), (TW)r[k]);
-                }
+                for (int k = 0; k < CPT; ++k)
+                    if (full || k < kact) bstore(slab, voff_w, rb + k * DT * (int)sizeof(TW), (TW)r[k]);
             }
 
             // Argmax of ALC_{i+1} over live candidates (needed from step n0 on).
@@ -755,14 +706,64 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (i + 1 >= n0) {
                 bv = redv[0]; bi = redi[0]; bs = reds[0];
                 for (int w = 1; w < DWAVES; ++w) pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
-                if (bs < 0 || bv == -INFINITY) { notpd = 1; break; }
+                if (bs < 0 || bv == -INFINITY) { notpd = 1; continue; }
                 s_next = bs;
                 // Stopping rule: the best candidate would shrink v(x) by less
                 // than the factor vratio (v_{i+1}(x) was published before B2).
                 if (A.vratio > 0.0) {
                     const double vx = misc[1];
                     const double vnext = vx - bv;
-                    if (vnext > 0.0 && vx / vnext < A.vratio) { nuse = i + 1; break; }
+                    if (vnext > 0.0 && vx / vnext < A.vratio) nuse = i + 1;
+                }
+            }
+        }
+
+        // ---- the last point: its column of W, K(s, x) and y_s give row n-1
+        //      of w_x and u (no candidate row is needed).
+        if (!notpd && nuse == n && n >= 1) {
+            const int i = n - 1;
+            const int s = (i < n0) ? forced[i] : s_next;
+            if (s < 0 || s >= M) {
+                notpd = 1;
+            } else {
+                const int s_lane = s % DT;
+                if (tid == s_lane) {
+                    const int kk = __builtin_amdgcn_readfirstlane(s / DT);
+#pragma unroll
+                    for (int k = 0; k < CPT; ++k) {
+                        if (k == kk) {
+#pragma unroll
+                            for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
+                                if (l < i) ws[l] = Wr[l][k];
+                            misc[0] = v[k];
+                            ctl[1] = ci[k];
+                        }
+                    }
+                }
+                for (int l = RREG + tid; l < i; l += DT)
+                    ws[l] = (l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s];
+                __syncthreads();
+                const double vs = misc[0];
+                if (!(vs > 0.0)) {
+                    notpd = 1;
+                } else if (tid == 0) {
+                    const double delta = sqrt(vs);
+                    const double rdelta = 1.0 / delta;
+                    double sqx = 0.0;
+                    for (int kk = 0; kk < p; ++kk) {
+                        const double tx = Xc[(int64_t)kk * Mpad + s] - xl[kk];
+                        sqx += tx * tx;
+                    }
+                    double ax = exp(-div_by(sqx, theta, rtheta));
+                    double ay = (CL && ylds) ? Xc[(int64_t)p * Mpad + s] : A.y[cand[s]];
+                    for (int l = 0; l < i; ++l) {
+                        const double wl = ws[l];
+                        ax -= wl * (double)wx[l];
+                        ay -= wl * uu[l];
+                    }
+                    wx[i] = div_by(ax, delta, rdelta);
+                    uu[i] = div_by(ay, delta, rdelta);
+                    if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
                 }
             }
         }
