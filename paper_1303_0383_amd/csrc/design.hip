@@ -17,14 +17,22 @@ static int launch_any(const DesignArgs* a, const DesignPlan& plan, hipStream_t s
 }
 
 // ------------------------------------------------------------------ plan
-static size_t fixed_lds_bytes(int nmax, int p, int dt)
+static size_t fixed_lds_bytes(int nmax, int p, int dt, bool mix)
 {
     const int dw = dt / 64;
+    const int nred = 2 * dw + (mix ? dw * (dw < 4 ? dw : 4) : 0);
     nmax = (nmax + 3) & ~3;
     size_t b = 0;
-    b += (size_t)(3 * nmax + 2 * p + 1 + 4 + 2 * dw) * sizeof(double);
-    b += (size_t)(4 * dw + nmax + 4) * sizeof(int);
-    return (b + 15) & ~(size_t)15;
+    b += (size_t)(3 * nmax + 2 * p + 1 + 4 + nred) * sizeof(double);
+    b += (size_t)(2 * nred + nmax + 4) * sizeof(int);
+    b = (b + 15) & ~(size_t)15;
+    if (mix) {
+        // exact factor (packed), delta, 1/delta, w_x, staged columns; slots, staged ids
+        size_t m = (size_t)(packed_row(nmax) + 3 * nmax + dw * (nmax + 4)) * sizeof(double);
+        m += (size_t)(nmax + 2 * dw) * sizeof(int);
+        b += (m + 15) & ~(size_t)15;
+    }
+    return b;
 }
 
 // Global-memory row reads per location (in candidate rows) when rows
@@ -49,7 +57,8 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     const int Mpad = cpt * dt;
     const int p = D.p;
     const int rows = nmax > 1 ? nmax - 1 : 0;  // W rows ever stored
-    const size_t fixed = fixed_lds_bytes(nmax, p, dt);
+    if (mix && nmax > 128) { *err = "the mixed precision mode supports n <= 128"; return -1; }
+    const size_t fixed = fixed_lds_bytes(nmax, p, dt, mix);
     if (fixed > max_lds) { *err = "local design size too large for LDS"; return -1; }
     const size_t row_bytes = (size_t)Mpad * (mix ? sizeof(float) : sizeof(double));   // tile row
     const size_t crow_bytes = (size_t)Mpad * sizeof(double);                          // coordinate row

@@ -117,6 +117,18 @@ __device__ __forceinline__ double dpp_d(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A double from lane `l` of the wave (l uniform).
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Offset of row l of a packed lower triangle (row l holds l + 1 entries).
+__host__ __device__ __forceinline__ int packed_row(int l) { return l * (l + 1) / 2; }
+
 // Candidate ordering for the argmax: larger score first, then smaller index.
 __device__ __forceinline__ bool better(double a, int ia, double b, int ib)
 {
@@ -313,13 +325,31 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     double* xl = uu + nmax;          // [p]    predictive location
     double* xsl = xl + p;            // [p+1]  (spare)
     double* misc = xsl + p + 1;      // [4]    v_s, v_j(x)
-    double* redv = misc + 4;         // [2*DWAVES] per-wave best scores
-    int* redi = (int*)(redv + 2 * DWAVES);  // [2*DWAVES] best design index
-    int* reds = redi + 2 * DWAVES;          // [2*DWAVES] best slot
-    int* forced = reds + 2 * DWAVES;        // [nmax] slots of the starting design
+    // per-wave best (score, design index, slot); the mixed mode adds each
+    // wave's DWAVES best by the FP32-tile scores
+    constexpr int NSHORT = DWAVES < 4 ? DWAVES : 4;   // mixed mode: candidates re-scored per step
+    constexpr int NRED = 2 * DWAVES + (MIX ? DWAVES * NSHORT : 0);
+    double* redv = misc + 4;         // [NRED]
+    int* redi = (int*)(redv + NRED); // [NRED]
+    int* reds = redi + NRED;         // [NRED]
+    int* forced = reds + NRED;       // [nmax] slots of the starting design
     int* ctl = forced + nmax;               // [4]  location, chosen index, bad start, unset candidate
     size_t off = (size_t)((char*)(ctl + 4) - (char*)smem);
     off = (off + 15) & ~(size_t)15;
+    // Mixed mode: the exact FP64 factor of the chosen points (packed rows of
+    // L: row l holds W_l[0..l-1][s_l] and delta_l on the diagonal), delta_l and
+    // 1/delta_l, the exact L^{-1}k(x) (u = L^{-1}Y is uu), the chosen slots,
+    // and per wave one staged exact column with its v, cov(x, .), y-row and
+    // score (then design index and slot).
+    const int npk = packed_row(nmax);
+    double* Lf = (double*)((char*)smem + off);   // [npk]
+    double* dl = Lf + npk;                       // [nmax]
+    double* rdl = dl + nmax;                     // [nmax]
+    double* wx64 = rdl + nmax;                   // [nmax]
+    double* stg = wx64 + nmax;                   // [DWAVES][nmax + 4]
+    int* sslot = (int*)(stg + DWAVES * (nmax + 4));   // [nmax]
+    int* mxi = sslot + nmax;                     // [2 * DWAVES]
+    if (MIX) off = (((size_t)((char*)(mxi + 2 * DWAVES) - (char*)smem)) + 15) & ~(size_t)15;
     const int ylds = CL ? A.y_lds : 0;
     double* Xcl = (double*)((char*)smem + off);              // [p (+1)][Mpad] when CL: coordinates (y)
     TW* Wl = (TW*)(Xcl + (CL ? (size_t)(p + ylds) * Mpad : 0));  // [rlds][Mpad]
@@ -466,6 +496,32 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         int s_next = -1;
         int notpd = (theta_ok && !badstart && !nocand) ? 0 : 1;
         int nuse = n;   // design size reached (the stopping rule may end the search early)
+        double vxr = one_eta;   // exact v_j(x) (mixed mode), the same in every thread
+        if constexpr (MIX) {
+            // Row 0 of the exact factor: the first point's column is empty and
+            // v_0(s_0) = 1 + g; its rows of w_x and u follow from K(s_0, x), y_s0.
+            const int s0 = forced[0];
+            if (!notpd && (s0 < 0 || s0 >= M)) notpd = 1;
+            if (!notpd) {
+                const double delta = sqrt(one_eta);
+                const double rdelta = 1.0 / delta;
+                double sq = 0.0;
+                for (int kk = 0; kk < p; ++kk) {
+                    const double tx = xl[kk] - Xc[(int64_t)kk * Mpad + s0];
+                    sq += tx * tx;
+                }
+                const double rx = div_by(exp(-div_by(sq, theta, rtheta)), delta, rdelta);
+                vxr -= rx * rx;
+                if (tid == 0) {
+                    Lf[0] = delta;
+                    dl[0] = delta;
+                    rdl[0] = rdelta;
+                    wx64[0] = rx;
+                    uu[0] = div_by(A.y[cand[s0]], delta, rdelta);
+                    sslot[0] = s0;
+                }
+            }
+        }
         // Full steps i = 0 .. n-2 append row i of W for every candidate and
         // choose the next point; the last chosen point is appended after the
         // loop (only its own column is needed there).
@@ -562,9 +618,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             for (int k = 0; k < CPT; ++k) dot[k] = 0.0f;
             __syncthreads();   // B1: column of s and v(s) published
 
+            // The mixed mode's FP32 ranking stays self-consistent: its delta
+            // is that of the tile's own v(s) (the exact one if that is not
+            // positive); the exact factor is kept apart.
             const double vs = misc[0];
-            if (!(vs > 0.0)) { notpd = 1; continue; }
-            const double delta = sqrt(vs);
+            if (!MIX && !(vs > 0.0)) { notpd = 1; continue; }
+            const double delta = (MIX && !(vs > 0.0)) ? dl[i] : sqrt(vs);
             const double rdelta = 1.0 / delta;
             double ay = ys;
             // Row i of W for every live candidate: acc = K(s,c) - sum_l ws[l] W[l][c].
@@ -652,9 +711,11 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             const double rx = MIX ? ax * rdelta : div_by(ax, delta, rdelta);
             if (tid == 0) {
                 wx[i] = rx;
-                uu[i] = div_by(ay, delta, rdelta);
+                if (!MIX) {
+                    uu[i] = div_by(ay, delta, rdelta);
+                    misc[1] -= rx * rx;
+                }
                 if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
-                misc[1] -= rx * rx;
             }
             double r[CPT];
 #pragma unroll
@@ -686,41 +747,213 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             // reciprocal of v.
             double bv = -INFINITY;
             int bi = 0x7fffffff, bs = -1;
-            if (i + 1 >= n0) {
+            if constexpr (!MIX) {
+                if (i + 1 >= n0) {
 #pragma unroll
-                for (int k = 0; k < CPT; ++k) {
-                    if (!((chosen >> k) & 1u)) {
+                    for (int k = 0; k < CPT; ++k) {
+                        if (!((chosen >> k) & 1u)) {
+                            double a = -INFINITY;
+                            if (v[k] > 0.0) {
+                                double y = __builtin_amdgcn_rcp(v[k]);
+                                y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
+                                a = (cov[k] * cov[k]) * y;
+                            }
+                            if (bs < 0 || better(a, ci[k], bv, bi)) { bv = a; bi = ci[k]; bs = tid + k * DT; }
+                        }
+                    }
+                    wave_pick<true>(bv, bi, bs);
+                    if (lane == 0) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
+                }
+            } else {
+                // Mixed mode: a short list of the DWAVES best candidates by the
+                // FP32-tile scores (ties to the smaller design index, so the
+                // list does not depend on where candidates sit), each wave
+                // contributing its own DWAVES best.
+                if (i + 1 >= n0) {
+                    double sc[CPT];
+#pragma unroll
+                    for (int k = 0; k < CPT; ++k) {
                         double a = -INFINITY;
                         if (v[k] > 0.0) {
                             double y = __builtin_amdgcn_rcp(v[k]);
                             y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
                             a = (cov[k] * cov[k]) * y;
                         }
-                        if (bs < 0 || better(a, ci[k], bv, bi)) { bv = a; bi = ci[k]; bs = tid + k * DT; }
+                        sc[k] = a;
+                    }
+                    // the wave's NSHORT best: each round every thread offers its
+                    // best slot not yet taken, and the winner's thread marks it taken
+                    uint32_t taken = chosen;
+#pragma unroll
+                    for (int q = 0; q < NSHORT; ++q) {
+                        double tv = -INFINITY;
+                        int ti = 0x7fffffff, ts = -1;
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k)
+                            if (!((taken >> k) & 1u) && (ts < 0 || better(sc[k], ci[k], tv, ti))) {
+                                tv = sc[k]; ti = ci[k]; ts = tid + k * DT;
+                            }
+                        wave_pick<true>(tv, ti, ts);
+                        ts = __builtin_amdgcn_readfirstlane(ts);
+                        if (lane == 0) {
+                            redv[2 * DWAVES + wave * NSHORT + q] = tv;
+                            redi[2 * DWAVES + wave * NSHORT + q] = ti;
+                            reds[2 * DWAVES + wave * NSHORT + q] = ts;
+                        }
+                        if (ts >= 0 && ts % DT == tid) taken |= 1u << (ts / DT);
                     }
                 }
-                wave_pick<true>(bv, bi, bs);
-                if (lane == 0) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
             }
             __syncthreads();   // B2: partial maxima published; everyone is done with ws
-            if (i + 1 >= n0) {
+            if constexpr (MIX) {
+                // Each wave re-scores one short-listed candidate exactly in FP64
+                // (its column of W by forward substitution against the exact
+                // factor, in the order the FP64 kernel uses, so the score is the
+                // FP64 kernel's) and stages it.  Before step n0 the next point
+                // is the next starting point: wave 0 computes its column.
+                int sa = -1, ia = 0x7fffffff;
+                if (i + 1 >= n0 && wave < NSHORT) {
+                    // the global list: round q takes the best entry not yet taken
+                    const int nl = DWAVES * NSHORT;
+                    double ev = lane < nl ? redv[2 * DWAVES + lane] : -INFINITY;
+                    int ei = lane < nl ? redi[2 * DWAVES + lane] : 0x7fffffff;
+                    int es = lane < nl ? reds[2 * DWAVES + lane] : -1;
+                    for (int q = 0; q <= wave; ++q) {
+                        double tv = ev;
+                        int ti = ei, ts = es;
+                        wave_pick<true>(tv, ti, ts);
+                        ti = __builtin_amdgcn_readfirstlane(ti);
+                        ts = __builtin_amdgcn_readfirstlane(ts);
+                        if (q == wave) { sa = ts; ia = ti; }
+                        if (ts >= 0 && es == ts) { ev = -INFINITY; ei = 0x7fffffff; es = -1; }
+                    }
+                } else if (wave == 0) {
+                    sa = forced[i + 1];
+                }
+                const int jr = i + 1;   // rows of the exact column: design points 0..i
+                double* rec = stg + wave * (nmax + 4);
+                double bvw = -INFINITY;
+                int biw = 0x7fffffff, bsw = -1;
+                if (sa >= 0 && sa < M) {
+                    // K(s_l, c) for the rows l = lane, lane + 64
+                    auto kdist = [&](int sl, int sc) {
+                        double sq = 0.0;
+                        for (int kk = 0; kk < p; ++kk) {
+                            const double tt = Xc[(int64_t)kk * Mpad + sl] - Xc[(int64_t)kk * Mpad + sc];
+                            sq += tt * tt;
+                        }
+                        return exp(-div_by(sq, theta, rtheta));
+                    };
+                    double a0 = 0.0, a1 = 0.0;
+                    if (lane < jr) a0 = kdist(sslot[lane], sa);
+                    if (lane + 64 < jr) a1 = kdist(sslot[lane + 64], sa);
+                    double sqx = 0.0;
+                    for (int kk = 0; kk < p; ++kk) {
+                        const double tt = xl[kk] - Xc[(int64_t)kk * Mpad + sa];
+                        sqx += tt * tt;
+                    }
+                    double vA = one_eta, cA = exp(-div_by(sqx, theta, rtheta)), yA = A.y[cand[sa]];
+                    double w0 = 0.0, w1 = 0.0;
+                    const int r0 = packed_row(lane), r1 = packed_row(lane + 64);
+                    // delta_l, 1/delta_l, w_x[l], u[l] of row l = lane (+64) in
+                    // registers, broadcast from lane m inside the loop
+                    const double d0 = lane < jr ? dl[lane] : 1.0, q0 = lane < jr ? rdl[lane] : 1.0;
+                    const double x0 = lane < jr ? wx64[lane] : 0.0, y0 = lane < jr ? uu[lane] : 0.0;
+                    const double d1 = lane + 64 < jr ? dl[lane + 64] : 1.0, q1 = lane + 64 < jr ? rdl[lane + 64] : 1.0;
+                    const double x1 = lane + 64 < jr ? wx64[lane + 64] : 0.0, y1 = lane + 64 < jr ? uu[lane + 64] : 0.0;
+                    // the factor entries L[l][m] are read one iteration ahead
+                    double f0 = (0 < lane && lane < jr) ? Lf[r0] : 0.0;
+                    double f1 = (lane + 64 < jr) ? Lf[r1] : 0.0;
+                    for (int m = 0; m < jr; ++m) {
+                        const int ml = m & 63;
+                        const bool lo = m < 64;
+                        const double W = div_by(readlane_d(lo ? a0 : a1, ml), readlane_d(lo ? d0 : d1, ml),
+                                                readlane_d(lo ? q0 : q1, ml));
+                        const double xm = readlane_d(lo ? x0 : x1, ml), ym = readlane_d(lo ? y0 : y1, ml);
+                        const double g0 = f0, g1 = f1;
+                        f0 = (m + 1 < lane && lane < jr) ? Lf[r0 + m + 1] : 0.0;
+                        f1 = (m + 1 < lane + 64 && lane + 64 < jr) ? Lf[r1 + m + 1] : 0.0;
+                        vA -= W * W;
+                        cA -= xm * W;
+                        yA -= ym * W;
+                        if (lane == ml) {
+                            if (lo) w0 = W;
+                            else w1 = W;
+                        }
+                        if (lane > m && lane < jr) a0 -= g0 * W;
+                        if (lane + 64 > m && lane + 64 < jr) a1 -= g1 * W;
+                    }
+                    if (lane < jr) rec[lane] = w0;
+                    if (lane + 64 < jr) rec[lane + 64] = w1;
+                    if (vA > 0.0) {
+                        double y = __builtin_amdgcn_rcp(vA);
+                        y = __builtin_fma(__builtin_fma(-vA, y, 1.0), y, y);
+                        bvw = (cA * cA) * y;
+                    }
+                    biw = ia;
+                    bsw = sa;
+                    if (lane == 0) {
+                        rec[nmax] = vA;
+                        rec[nmax + 1] = cA;
+                        rec[nmax + 2] = yA;
+                    }
+                }
+                if (lane == 0) { redv[wave] = bvw; redi[wave] = biw; reds[wave] = bsw; }
+                __syncthreads();   // B3: exact scores staged
+            }
+            if (MIX || i + 1 >= n0) {
                 bv = redv[0]; bi = redi[0]; bs = reds[0];
-                for (int w = 1; w < DWAVES; ++w) pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
-                if (bs < 0 || bv == -INFINITY) { notpd = 1; continue; }
+                int bw = 0;
+                for (int w = 1; w < DWAVES; ++w) {
+                    const int before = bs;
+                    pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
+                    if (bs != before) bw = w;
+                }
+                if (bs < 0 || (i + 1 >= n0 && bv == -INFINITY)) { notpd = 1; continue; }
                 s_next = bs;
+                double vx = misc[1];
+                double dN = 0.0, rdN = 0.0, rxN = 0.0;
+                const double* rec = stg + bw * (nmax + 4);
+                if constexpr (MIX) {
+                    // the chosen point's exact row of L, w_x and u
+                    const double vN = rec[nmax];
+                    if (!(vN > 0.0)) { notpd = 1; continue; }
+                    dN = sqrt(vN);
+                    rdN = 1.0 / dN;
+                    rxN = div_by(rec[nmax + 1], dN, rdN);
+                    vx = vxr;
+                }
                 // Stopping rule: the best candidate would shrink v(x) by less
                 // than the factor vratio (v_{i+1}(x) was published before B2).
-                if (A.vratio > 0.0) {
-                    const double vx = misc[1];
+                if (A.vratio > 0.0 && i + 1 >= n0) {
                     const double vnext = vx - bv;
                     if (vnext > 0.0 && vx / vnext < A.vratio) nuse = i + 1;
+                }
+                if (MIX && nuse == n) {
+                    vxr -= rxN * rxN;
+                    const int ro = packed_row(i + 1);
+                    for (int e = tid; e <= i; e += DT) Lf[ro + e] = rec[e];
+                    if (tid == 0) {
+                        Lf[ro + i + 1] = dN;
+                        dl[i + 1] = dN;
+                        rdl[i + 1] = rdN;
+                        wx64[i + 1] = rxN;
+                        uu[i + 1] = div_by(rec[nmax + 2], dN, rdN);
+                        sslot[i + 1] = bs;
+                    }
                 }
             }
         }
 
         // ---- the last point: its column of W, K(s, x) and y_s give row n-1
-        //      of w_x and u (no candidate row is needed).
-        if (!notpd && nuse == n && n >= 1) {
+        //      of w_x and u (no candidate row is needed).  The mixed mode
+        //      appended its exact row when the point was chosen.
+        if (MIX && !notpd && nuse == n && n >= 1) {
+            const int s = (n - 1 < n0) ? forced[n - 1] : s_next;
+            if (s < 0 || s >= M) notpd = 1;
+            else if (tid == 0 && A.sel) A.sel[t * A.sel_stride + n - 1] = cand[s];
+        }
+        if (!MIX && !notpd && nuse == n && n >= 1) {
             const int i = n - 1;
             const int s = (i < n0) ? forced[i] : s_next;
             if (s < 0 || s >= M) {
@@ -768,19 +1001,20 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             }
         }
 
-        // ---- prediction (eqs predgp, preds2 with N -> n); with an FP32 tile the
-        //      prediction kernel refactorises K_n in FP64 from the indices.
+        // ---- prediction (eqs predgp, preds2 with N -> n) from w_x and u; the
+        //      mixed mode uses its exact FP64 rows.
         __syncthreads();
-        if (tid == 0 && !MIX) {
+        if (tid == 0) {
             double mean, s2v, var;
             if (notpd) {
                 mean = s2v = var = NAN;
             } else {
                 double m = 0.0, ps = 0.0, q = 0.0;
                 for (int l = 0; l < nuse; ++l) {
-                    m += wx[l] * uu[l];
+                    const double wl = MIX ? wx64[l] : (double)wx[l];
+                    m += wl * uu[l];
                     ps += uu[l] * uu[l];
-                    q += wx[l] * wx[l];
+                    q += wl * wl;
                 }
                 const double vxn = one_eta - q;
                 mean = m;
@@ -793,8 +1027,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (A.df) A.df[t] = nuse;
             if (A.status) A.status[t] = nocand ? 3 : badstart ? 2 : notpd ? 1 : 0;
         }
-        // the mixed mode's FP64 prediction reads the design size reached
-        if (MIX && tid == 0 && A.vratio > 0.0 && A.df) A.df[t] = nuse;
         __syncthreads();
     }
 }

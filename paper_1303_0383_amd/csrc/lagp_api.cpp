@@ -319,11 +319,10 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
     }
     if (Mmax > 4096) return fail(LAGP_E_INVAL, "ncand above 4096 is not supported");
     if (nmax > 1024) return fail(LAGP_E_INVAL, "n above 1024 is not supported");
-    if (P->mix && lagp::predict_lds_bytes(nmax) > d->max_lds)
-        return fail(LAGP_E_INVAL, "n too large for the FP64 prediction kernel of the mixed mode");
+    if (P->mix && nmax > 128) return fail(LAGP_E_INVAL, "the mixed precision mode supports n <= 128");
     P->nmax = nmax;
     P->Mmax = Mmax;
-    P->own_sel = P->mix && !have_sel;
+    P->own_sel = false;
     P->own_status = P->mix && !have_status;
     const int64_t tc_max = std::min(chunk, std::max<int64_t>(T, 1));
     size_t design_b = 0;
@@ -423,7 +422,7 @@ int prepare_plan(const lagp_design* d, const Plan& P)
             if (lagp::design_prepare(b.plan, &err)) return fail(LAGP_E_HIP, err);
         if (P.mix && lagp::design_prepare(c.redo, &err)) return fail(LAGP_E_HIP, err);
     }
-    if ((P.mix || P.alc2) && lagp::predict_prepare(P.nmax, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
+    if (P.alc2 && lagp::predict_prepare(P.nmax, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
     if (P.alc2 && lagp::mle_prepare(P.nmax, d->dev.p, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
     return LAGP_OK;
 }
@@ -485,15 +484,11 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     }
     if (P.mix) {
-        // with the stopping rule the design kernel has written the size reached into df
-        const int32_t* sizes = L.vratio > 0.0 ? L.df : L.n_per;
-        int r = lagp::predict_run(d->dev, L.XX, c.T, L.sel, L.sel_stride, sizes, c.nmax, L.theta, L.theta_per, L.eta,
-                                  L.mean, L.s2, L.df, L.var, L.status, d->max_lds, s, &err);
-        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
-        // FP32 ranking can lose positive definiteness where FP64 keeps it
-        // (tiny nuggets, near-duplicate neighbours): the locations that
-        // failed are redone in FP64 from a device-side list.
+        // A location the mixed mode could not finish (its short list held no
+        // candidate with a positive exact variance) is redone in FP64 from a
+        // device-side list.
         lagp::fill_u32(redo_count, 1, 0u, s);
+        int r;
         hipLaunchKernelGGL(collect_failed_kernel, dim3((unsigned)((c.T + 255) / 256)), dim3(256), 0, s, L.status,
                            c.T, redo_list, redo_count);
         L.precision = LAGP_PREC_FP64;
@@ -599,7 +594,7 @@ int enqueue_plan(lagp_design* d, const Plan& P, char* ws, const int32_t* order_d
         L.s2 = o.s2 + c.t0;
         L.df = o.df ? o.df + c.t0 : nullptr;
         L.var = o.var ? o.var + c.t0 : nullptr;
-        L.sel = o.sel ? o.sel + c.t0 * o.sel_stride : sel_ws;
+        L.sel = o.sel ? o.sel + c.t0 * o.sel_stride : (P.own_sel ? sel_ws : nullptr);
         L.sel_stride = o.sel ? o.sel_stride : P.nmax;
         L.status = o.status ? o.status + c.t0 : (P.own_status ? st_ws + c.t0 : nullptr);
         if (!P.alc2) {

@@ -156,6 +156,10 @@ def test_batch_mixed_precision(c3, lagp):
     for rep in range(2):
         _same(_host(B.run(XXd, graph=True)), ref, sub.n_per)
     B.close()
+    m = mixed_metrics(sub.X, sub.y, sub.XX, sub.n0, sub.n, sub.ncand, sub.d, sub.g, ref, idx=range(0, 600, 10),
+                      n_per=sub.n_per, M_per=sub.ncand_per)
+    print("c3 mixed", m)
+    assert m["step_agreement"] >= 0.99 and m["mean_rms_over_sd"] <= 1e-4
 
 
 def test_mixed_redo_on_device(c1, lagp):

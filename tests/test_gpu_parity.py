@@ -311,14 +311,21 @@ def test_mixed_precision_c2(c2, lagp, n):
     print("mixed c2 n=%d" % n, m)
     assert m["step_agreement"] >= 0.99
     assert m["prediction_parity"] <= 1e-9
-    # The mean RMS against the FP64 oracle is reported: locations whose greedy
-    # sequence takes a different near-tied step have a different (equally
-    # valid) local design, and their prediction moves by the local model error.
-    assert m["mean_rms_over_sd"] <= 1e-2
+    assert m["mean_rms_over_sd"] <= 1e-4
+    # The short list is re-scored exactly in FP64 in the FP64 kernel's
+    # operation order: where the sequences agree, the outputs are the FP64
+    # path's bit for bit.
+    ref = gpu_predict(D, XX, w.n0, n, w.ncand, w.d, w.g)
+    same = np.all(res["sel"][:, :n] == ref["sel"][:, :n], axis=1)
+    assert same.mean() >= 0.99, same.mean()
+    for k in ("mean", "s2", "var"):
+        assert np.array_equal(res[k][same], ref[k][same]), k
 
 
 def test_mixed_precision_c1_reported(c1, lagp):
-    # The 2-D workload has nugget 1e-6; FP32 ranking there is reported, not gated.
+    # The 2-D workload has nugget 1e-6: the FP32 tile cannot resolve v_j(c)
+    # near g (its sums are of order 1), so its short list often misses the
+    # FP64 winner.  Reported here; the bar is gated (and expected to fail) below.
     w, D = c1
     XX = w.XX[::211]
     res = gpu_predict(D, XX, w.n0, w.n, w.ncand, w.d, w.g, precision=lagp.LAGP_PREC_SCORE_FP32)
@@ -326,3 +333,13 @@ def test_mixed_precision_c1_reported(c1, lagp):
     m = mixed_metrics(w.X, w.y, XX, w.n0, w.n, w.ncand, w.d, w.g, res, idx=range(0, len(XX), 2))
     print("mixed c1", m)
     assert m["prediction_parity"] <= 1e-9
+
+
+@pytest.mark.xfail(strict=True, reason="FP32 ranking cannot resolve v_j(c) near the 1e-6 nugget of the 2-D workload")
+def test_mixed_precision_c1_bar(c1, lagp):
+    w, D = c1
+    XX = w.XX[::211]
+    res = gpu_predict(D, XX, w.n0, w.n, w.ncand, w.d, w.g, precision=lagp.LAGP_PREC_SCORE_FP32)
+    from parity import mixed_metrics
+    m = mixed_metrics(w.X, w.y, XX, w.n0, w.n, w.ncand, w.d, w.g, res, idx=range(0, len(XX), 2))
+    assert m["step_agreement"] >= 0.99 and m["mean_rms_over_sd"] <= 1e-4
