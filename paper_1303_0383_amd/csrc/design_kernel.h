@@ -237,6 +237,40 @@ __device__ __forceinline__ void wave_pick(double& v, int& i, int& s)
     pick<MAX>(v, i, s, __shfl_xor(v, 32), __shfl_xor(i, 32), __shfl_xor(s, 32));
 }
 
+// Order-preserving 64-bit key of (score, design index) for short lists:
+// larger score first, then smaller index.  The score is rounded to float, so
+// scores within float rounding of each other rank by index; 0 marks no entry.
+__device__ __forceinline__ uint64_t rank_key(double a, int idx)
+{
+    const uint32_t hi = a > 0.0 ? __float_as_uint((float)a) : 0u;
+    return ((uint64_t)hi << 32) | (uint32_t)(0xffffffffu - (uint32_t)idx);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_key(uint64_t k)
+{
+    const int lo = (int)(uint32_t)k, hi = (int)(uint32_t)(k >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    return ((uint64_t)(uint32_t)h2 << 32) | (uint32_t)l2;
+}
+
+// Largest key of the wave: row maxima by quad permutes and row rotations,
+// then row broadcasts carry them into lane 63, which is read back.
+__device__ __forceinline__ uint64_t wave_max_key(uint64_t k)
+{
+    uint64_t o;
+    o = dpp_key<0xB1, 0xF>(k);  k = o > k ? o : k;   // xor 1
+    o = dpp_key<0x4E, 0xF>(k);  k = o > k ? o : k;   // xor 2
+    o = dpp_key<0x124, 0xF>(k); k = o > k ? o : k;   // rotate 4 in row
+    o = dpp_key<0x128, 0xF>(k); k = o > k ? o : k;   // rotate 8 in row
+    o = dpp_key<0x142, 0xA>(k); k = o > k ? o : k;   // lane 15 of rows 0, 2 into rows 1, 3
+    o = dpp_key<0x143, 0xC>(k); k = o > k ? o : k;   // lane 31 into rows 2, 3
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)k, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // ---- the per-workgroup global slab through a buffer descriptor: one
 // per-thread offset register and uniform (scalar) slot and row offsets, so no
 // address registers per (slot, row) pair; accesses past the slab read 0 and
@@ -517,7 +551,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     dl[0] = delta;
                     rdl[0] = rdelta;
                     wx64[0] = rx;
-                    uu[0] = div_by(A.y[cand[s0]], delta, rdelta);
                     sslot[0] = s0;
                 }
             }
@@ -781,26 +814,29 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         }
                         sc[k] = a;
                     }
-                    // the wave's NSHORT best: each round every thread offers its
-                    // best slot not yet taken, and the winner's thread marks it taken
-                    uint32_t taken = chosen;
+                    // the wave's NSHORT best keys: each round takes the wave's
+                    // largest key, and the thread holding it clears it and
+                    // publishes its slot (keys are unique)
+                    uint64_t key[CPT];
+#pragma unroll
+                    for (int k = 0; k < CPT; ++k) key[k] = ((chosen >> k) & 1u) ? 0ull : rank_key(sc[k], ci[k]);
 #pragma unroll
                     for (int q = 0; q < NSHORT; ++q) {
-                        double tv = -INFINITY;
-                        int ti = 0x7fffffff, ts = -1;
+                        uint64_t t = 0;
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) t = key[k] > t ? key[k] : t;
+                        t = wave_max_key(t);
+                        const int e = 2 * DWAVES + wave * NSHORT + q;
+                        if (lane == 0) {
+                            redv[e] = __longlong_as_double((long long)t);
+                            if (t == 0) reds[e] = -1;
+                        }
 #pragma unroll
                         for (int k = 0; k < CPT; ++k)
-                            if (!((taken >> k) & 1u) && (ts < 0 || better(sc[k], ci[k], tv, ti))) {
-                                tv = sc[k]; ti = ci[k]; ts = tid + k * DT;
+                            if (t != 0 && key[k] == t) {
+                                reds[e] = tid + k * DT;
+                                key[k] = 0;
                             }
-                        wave_pick<true>(tv, ti, ts);
-                        ts = __builtin_amdgcn_readfirstlane(ts);
-                        if (lane == 0) {
-                            redv[2 * DWAVES + wave * NSHORT + q] = tv;
-                            redi[2 * DWAVES + wave * NSHORT + q] = ti;
-                            reds[2 * DWAVES + wave * NSHORT + q] = ts;
-                        }
-                        if (ts >= 0 && ts % DT == tid) taken |= 1u << (ts / DT);
                     }
                 }
             }
@@ -813,19 +849,17 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 // is the next starting point: wave 0 computes its column.
                 int sa = -1, ia = 0x7fffffff;
                 if (i + 1 >= n0 && wave < NSHORT) {
-                    // the global list: round q takes the best entry not yet taken
+                    // the global list: wave w takes the entry of rank w among
+                    // all waves' keys (rank = number of larger keys)
                     const int nl = DWAVES * NSHORT;
-                    double ev = lane < nl ? redv[2 * DWAVES + lane] : -INFINITY;
-                    int ei = lane < nl ? redi[2 * DWAVES + lane] : 0x7fffffff;
-                    int es = lane < nl ? reds[2 * DWAVES + lane] : -1;
-                    for (int q = 0; q <= wave; ++q) {
-                        double tv = ev;
-                        int ti = ei, ts = es;
-                        wave_pick<true>(tv, ti, ts);
-                        ti = __builtin_amdgcn_readfirstlane(ti);
-                        ts = __builtin_amdgcn_readfirstlane(ts);
-                        if (q == wave) { sa = ts; ia = ti; }
-                        if (ts >= 0 && es == ts) { ev = -INFINITY; ei = 0x7fffffff; es = -1; }
+                    const uint64_t ke = lane < nl ? (uint64_t)__double_as_longlong(redv[2 * DWAVES + lane]) : 0ull;
+                    int rank = 0;
+                    for (int j = 0; j < nl; ++j) rank += (uint64_t)__double_as_longlong(redv[2 * DWAVES + j]) > ke;
+                    const uint64_t own = __ballot(lane < nl && ke != 0 && rank == wave);
+                    if (own) {
+                        const int el = __builtin_ctzll(own);
+                        sa = reds[2 * DWAVES + el];
+                        ia = (int)(0xffffffffu - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ke, el));
                     }
                 } else if (wave == 0) {
                     sa = forced[i + 1];
@@ -852,37 +886,44 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         const double tt = xl[kk] - Xc[(int64_t)kk * Mpad + sa];
                         sqx += tt * tt;
                     }
-                    double vA = one_eta, cA = exp(-div_by(sqx, theta, rtheta)), yA = A.y[cand[sa]];
+                    double vA = one_eta, cA = exp(-div_by(sqx, theta, rtheta));
                     double w0 = 0.0, w1 = 0.0;
-                    const int r0 = packed_row(lane), r1 = packed_row(lane + 64);
-                    // delta_l, 1/delta_l, w_x[l], u[l] of row l = lane (+64) in
-                    // registers, broadcast from lane m inside the loop
-                    const double d0 = lane < jr ? dl[lane] : 1.0, q0 = lane < jr ? rdl[lane] : 1.0;
-                    const double x0 = lane < jr ? wx64[lane] : 0.0, y0 = lane < jr ? uu[lane] : 0.0;
-                    const double d1 = lane + 64 < jr ? dl[lane + 64] : 1.0, q1 = lane + 64 < jr ? rdl[lane + 64] : 1.0;
-                    const double x1 = lane + 64 < jr ? wx64[lane + 64] : 0.0, y1 = lane + 64 < jr ? uu[lane + 64] : 0.0;
-                    // the factor entries L[l][m] are read one iteration ahead
-                    double f0 = (0 < lane && lane < jr) ? Lf[r0] : 0.0;
-                    double f1 = (lane + 64 < jr) ? Lf[r1] : 0.0;
-                    for (int m = 0; m < jr; ++m) {
-                        const int ml = m & 63;
-                        const bool lo = m < 64;
-                        const double W = div_by(readlane_d(lo ? a0 : a1, ml), readlane_d(lo ? d0 : d1, ml),
-                                                readlane_d(lo ? q0 : q1, ml));
-                        const double xm = readlane_d(lo ? x0 : x1, ml), ym = readlane_d(lo ? y0 : y1, ml);
-                        const double g0 = f0, g1 = f1;
-                        f0 = (m + 1 < lane && lane < jr) ? Lf[r0 + m + 1] : 0.0;
-                        f1 = (m + 1 < lane + 64 && lane + 64 < jr) ? Lf[r1 + m + 1] : 0.0;
-                        vA -= W * W;
-                        cA -= xm * W;
-                        yA -= ym * W;
-                        if (lane == ml) {
-                            if (lo) w0 = W;
-                            else w1 = W;
+                    // Column-oriented forward substitution over rows l = lane
+                    // (and lane + 64): row l subtracts L[l][m] W_m in ascending
+                    // m, as the FP64 kernel does.  Rows at or above m and lanes
+                    // past jr update too but are never read again, so no lane
+                    // predicate is needed.  delta_m, 1/delta_m, w_x[m] and L[l][m]
+                    // are read one iteration ahead; every read stays in LDS: a
+                    // lane past jr reads from row 0, and row l's reads end at
+                    // packed_row(l) + jr <= packed_row(jr) <= npk.
+                    auto solve = [&](auto two) {
+                        constexpr bool TWO = decltype(two)::value;
+                        const int r0 = lane < jr ? packed_row(lane) : 0;
+                        const int r1 = (TWO && lane + 64 < jr) ? packed_row(lane + 64) : 0;
+                        double dm = dl[0], rm = rdl[0], xm = wx64[0];
+                        double f0 = Lf[r0], f1 = TWO ? Lf[r1] : 0.0;
+                        for (int m = 0; m < jr; ++m) {
+                            const double dn = dl[m + 1], rn = rdl[m + 1], xn = wx64[m + 1];
+                            const double g0 = f0, g1 = f1;
+                            f0 = Lf[r0 + m + 1];
+                            if constexpr (TWO) f1 = Lf[r1 + m + 1];
+                            const double am = (!TWO || m < 64) ? readlane_d(a0, m & 63) : readlane_d(a1, m & 63);
+                            const double W = div_by(am, dm, rm);
+                            vA -= W * W;
+                            cA -= xm * W;
+                            w0 = lane == m ? W : w0;
+                            a0 -= g0 * W;
+                            if constexpr (TWO) {
+                                w1 = lane + 64 == m ? W : w1;
+                                a1 -= g1 * W;
+                            }
+                            dm = dn;
+                            rm = rn;
+                            xm = xn;
                         }
-                        if (lane > m && lane < jr) a0 -= g0 * W;
-                        if (lane + 64 > m && lane + 64 < jr) a1 -= g1 * W;
-                    }
+                    };
+                    if (jr > 64) solve(std::integral_constant<bool, true>{});
+                    else solve(std::integral_constant<bool, false>{});
                     if (lane < jr) rec[lane] = w0;
                     if (lane + 64 < jr) rec[lane + 64] = w1;
                     if (vA > 0.0) {
@@ -895,7 +936,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     if (lane == 0) {
                         rec[nmax] = vA;
                         rec[nmax + 1] = cA;
-                        rec[nmax + 2] = yA;
                     }
                 }
                 if (lane == 0) { redv[wave] = bvw; redi[wave] = biw; reds[wave] = bsw; }
@@ -938,7 +978,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         dl[i + 1] = dN;
                         rdl[i + 1] = rdN;
                         wx64[i + 1] = rxN;
-                        uu[i + 1] = div_by(rec[nmax + 2], dN, rdN);
                         sslot[i + 1] = bs;
                     }
                 }
@@ -952,6 +991,25 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             const int s = (n - 1 < n0) ? forced[n - 1] : s_next;
             if (s < 0 || s >= M) notpd = 1;
             else if (tid == 0 && A.sel) A.sel[t * A.sel_stride + n - 1] = cand[s];
+        }
+        if constexpr (MIX) {
+            // u = L^{-1} Y_n for the design reached, by forward substitution
+            // against the exact factor, each row in the order of the FP64
+            // kernel's u chain (ascending, y_s first): lane l holds row l.
+            __syncthreads();
+            if (!notpd && wave == 0) {
+                const int jn = nuse;
+                const int r0 = packed_row(lane), r1 = packed_row(lane + 64);
+                double a0 = lane < jn ? A.y[cand[sslot[lane]]] : 0.0;
+                double a1 = lane + 64 < jn ? A.y[cand[sslot[lane + 64]]] : 0.0;
+                for (int m = 0; m < jn; ++m) {
+                    const bool lo = m < 64;
+                    const double um = div_by(readlane_d(lo ? a0 : a1, m & 63), dl[m], rdl[m]);
+                    if (lane == 0) uu[m] = um;
+                    if (lane > m && lane < jn) a0 -= Lf[r0 + m] * um;
+                    if (lane + 64 > m && lane + 64 < jn) a1 -= Lf[r1 + m] * um;
+                }
+            }
         }
         if (!MIX && !notpd && nuse == n && n >= 1) {
             const int i = n - 1;
