@@ -190,6 +190,10 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=2000, help="c4: requests per offered-load level")
     ap.add_argument("--loads", default="0.5,0.8,0.95", help="c4: offered loads as fractions of saturation")
     ap.add_argument("--budget-gib", type=int, default=32, help="c4: serving HBM budget")
+    ap.add_argument("--serve-requests", type=int, default=500,
+                    help="requests of the serving leg of the default run (0: skip the leg)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="serving leg: offered load, fraction of saturation")
+    ap.add_argument("--serve-burst", type=int, default=128, help="serving leg: requests per saturating burst")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -495,8 +499,78 @@ def main() -> int:
             one_s = time.perf_counter() - tc
             result["cpu_baseline"]["single_thread"] = {"value": round(k1 / one_s, 2), "unit": "locations/s",
                                                        "sample": f"first {k1} locations of that sample, {one_s:.1f} s"}
+    if args.serve_requests > 0 and args.workload == "c2_n50" and args.method == "alc":
+        # request latency beside throughput: a short open-loop serving leg
+        result["serving"] = serving_leg(lagp, args)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def _saturate(S, prm, burst, steps, warmup):
+    """Locations/s of the server with `burst` submitted at once and drained,
+    over `steps` timed bursts after `warmup` untimed ones."""
+    def step():
+        ts = [S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"]) for r in burst]
+        for t in ts:
+            S.wait(t)
+
+    for _ in range(warmup):
+        step()
+    step_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        step()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
+    elapsed = time.perf_counter() - t0
+    return sum(len(r.XX) for r in burst) * steps / elapsed, elapsed, step_ms
+
+
+def _open_loop(S, lagp, prm, reqs, rate):
+    """Submit `reqs` at their Poisson arrival times (open loop); latency of a
+    request is its completion minus its scheduled arrival."""
+    mono = lagp.lagp_monotonic_seconds
+    b0 = S.stats()
+    start = mono() + 0.05
+    tickets = []
+    for r in reqs:
+        delay = start + r.arrival_s - mono()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"]))
+    lat, last = [], start
+    for r, t in zip(reqs, tickets):
+        o = S.wait(t)
+        lat.append(o.done - (start + r.arrival_s))
+        last = max(last, o.done)
+    b1 = S.stats()
+    locs = sum(len(r.XX) for r in reqs)
+    return {"offered_req_per_s": round(rate, 1), "requests": len(reqs),
+            "achieved_locations_per_s": round(locs / (last - start), 1),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+            "pieces": b1[0] - b0[0], "mean_piece_locations": round((b1[1] - b0[1]) / max(1, b1[0] - b0[0]), 1)}
+
+
+C4_MEAN_REQUEST = 256.5   # mean locations per serving request (uniform on 1..512)
+
+
+def serving_leg(lagp, args) -> dict:
+    """The default run's serving leg on the 4-D serving workload (N = 10^6):
+    saturation from bursts of --serve-burst requests, then --serve-requests
+    Poisson arrivals at --serve-load of saturation, FP64, open loop."""
+    import workloads
+    prm = workloads.C4_PARAMS
+    X, y, _ = workloads.c4_design()
+    D = lagp.Design(X, y)
+    S = lagp.Server(D, args.budget_gib << 30)
+    sat, _, _ = _saturate(S, prm, workloads.c4_requests(args.serve_burst, 1.0), steps=1, warmup=1)
+    rate = args.serve_load * sat / C4_MEAN_REQUEST
+    level = _open_loop(S, lagp, prm, workloads.c4_requests(args.serve_requests, rate), rate)
+    S.close()
+    D.close()
+    return {"workload": "c4", "N": len(X), "p": 4, "dtype": "f64", "budget_gib": args.budget_gib,
+            "saturation_locations_per_s": round(sat, 1), "load": args.serve_load, **level}
 
 
 def serve_bench(args, lagp, torch) -> int:
@@ -511,56 +585,13 @@ def serve_bench(args, lagp, torch) -> int:
     X, y, _ = workloads.c4_design()
     D = lagp.Design(X, y)
     S = lagp.Server(D, args.budget_gib << 30)
-    mono = lagp.lagp_monotonic_seconds
-
-    def submit(r):
-        return S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"])
-
     burst = workloads.c4_requests(args.burst, 1.0)
     burst_locs = sum(len(r.XX) for r in burst)
-
-    def step():
-        ts = [submit(r) for r in burst]
-        for t in ts:
-            S.wait(t)
-
-    for _ in range(args.warmup):
-        step()
-    step_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        step()
-        step_ms.append(1e3 * (time.perf_counter() - ts))
-    elapsed = time.perf_counter() - t0
-    sat = burst_locs * args.steps / elapsed
-    mean_T = 256.5
-
+    sat, elapsed, step_ms = _saturate(S, prm, burst, args.steps, args.warmup)
     levels = {}
     for load in [float(v) for v in args.loads.split(",") if v]:
-        rate = load * sat / mean_T
-        reqs = workloads.c4_requests(args.requests, rate)
-        b0 = S.stats()
-        start = mono() + 0.05
-        tickets = []
-        for r in reqs:
-            delay = start + r.arrival_s - mono()
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append(submit(r))
-        lat, last = [], start
-        for r, t in zip(reqs, tickets):
-            o = S.wait(t)
-            lat.append(o.done - (start + r.arrival_s))
-            last = max(last, o.done)
-        b1 = S.stats()
-        locs = sum(len(r.XX) for r in reqs)
-        levels[f"{load:.2f}"] = {
-            "offered_req_per_s": round(rate, 1), "requests": len(reqs),
-            "achieved_locations_per_s": round(locs / (last - start), 1),
-            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
-            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
-            "batches": b1[0] - b0[0], "mean_batch_locations": round((b1[1] - b0[1]) / max(1, b1[0] - b0[0]), 1)}
+        rate = load * sat / C4_MEAN_REQUEST
+        levels[f"{load:.2f}"] = _open_loop(S, lagp, prm, workloads.c4_requests(args.requests, rate), rate)
         print(f"# load {load:.2f}: {levels[f'{load:.2f}']}", file=sys.stderr, flush=True)
     S.close()
 

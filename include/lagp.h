@@ -284,21 +284,39 @@ void lagp_batch_destroy(lagp_batch *batch);
  * always uses 512); coords -1 (table or model), 0 candidate coordinates in
  * global memory, 1 in LDS when they fit.  Applies to later calls on `design`. */
 int lagp_design_set_variant(lagp_design *design, int32_t threads, int32_t coords);
+/* As lagp_design_set_variant, and the share of the LDS left after the fixed
+ * part that holds rows of the whitened candidate tile L^-1 K(X_j, candidates)
+ * (the factor form of the partitioned-inverse step, Supplementary Material
+ * Section 1): rows beyond those in registers go to LDS up to that share and
+ * the rest stream from global memory.  lds_rows_pct -1 (table, else 100) or
+ * 0..100; threads 0, coords -1 and lds_rows_pct -1 restore the table. */
+int lagp_design_set_variant_ex(lagp_design *design, int32_t threads, int32_t coords, int32_t lds_rows_pct);
 
 /* ---- Serving: continuous batching of requests under an HBM budget.
  *
- * A server owns a worker thread, a HIP stream and a device arena of
- * hbm_budget_bytes.  Submitted requests wait in a FIFO queue; whenever the
- * device is free the worker runs, as one batch, the oldest request together
- * with every later queued request of the same model (n0, d, g, precision)
- * while the batch's device footprint -- its plan workspace, inputs and
- * outputs -- fits the arena.  Each location's arithmetic is independent of
- * the batch it runs in (locations are independent, Section 4.1): a request's
- * results are bitwise the same alone or mixed with other traffic.
+ * A server owns a device arena of hbm_budget_bytes, `slots` HIP streams
+ * (default priority) and host threads that feed and drain them.  Submitted
+ * requests wait in a FIFO queue.  Their locations are cut into pieces of at
+ * most `piece_locations` locations of one model (n0, d, g, precision), taken
+ * in arrival order; a request may span pieces and a piece may hold several
+ * requests.  Up to `slots` pieces run at once, each on its own stream in its
+ * own first-fit region of the arena, so requests that arrive while others run
+ * are admitted as soon as a slot and memory are free and run beside them.  The
+ * last slot only takes requests that have not started, so a short request
+ * does not wait behind the rest of a long one.  A request completes when its
+ * last location's results are in (its own completion time).  Each location's
+ * arithmetic is independent of the piece it runs in (locations are
+ * independent, Section 4.1): a request's results are bitwise the same alone
+ * or mixed with other traffic.  Pieces in flight share no device memory:
+ * each has its own workspace.
  * All server arrays are HOST memory; inputs are copied at submission.
- * Calls are thread-safe.  The server must be destroyed before its design. */
+ * Calls are thread-safe.  The server must be destroyed before its design.
+ * slots: 0 (3) or 2..8; piece_locations: 0 (4096) or 1..131072; other
+ * values give LAGP_E_INVAL.  lagp_server_create uses the defaults. */
 typedef struct lagp_server lagp_server;
 int lagp_server_create(const lagp_design *design, size_t hbm_budget_bytes, lagp_server **out);
+int lagp_server_create_ex(const lagp_design *design, size_t hbm_budget_bytes, int32_t slots,
+                          int32_t piece_locations, lagp_server **out);
 
 /* Queue T locations XX (host, T x p) with per-location n / N' (host int32[T],
  * nullable: params values).  Checks as lagp_predict; params->flags must be 0.
@@ -312,16 +330,16 @@ int lagp_server_submit(lagp_server *server, const double *XX, int32_t T, const l
  * is done, releasing the ticket; 0 while it is pending.  wait_ms: 0 polls,
  * > 0 waits at most that long, < 0 waits for completion.  times (nullable)
  * receives [submission, completion] in seconds on the monotonic clock of
- * lagp_monotonic_seconds.  A failed batch returns its error code. */
+ * lagp_monotonic_seconds.  A request a failed piece held returns its error code. */
 int lagp_server_poll(lagp_server *server, uint64_t ticket, int32_t wait_ms, double *mean, double *s2, int32_t *df,
                      double *var, int32_t *sel, int64_t sel_stride, int8_t *status, double *times);
 
-/* Batches run, locations and requests completed, and seconds the worker spent
- * running batches, since creation. */
-int lagp_server_stats(lagp_server *server, int64_t *batches, int64_t *locations, int64_t *requests,
+/* Pieces dispatched, locations and requests completed, and seconds during
+ * which at least one piece was in flight, since creation. */
+int lagp_server_stats(lagp_server *server, int64_t *pieces, int64_t *locations, int64_t *requests,
                       double *busy_seconds);
 
-/* Finish the queued requests, stop the worker and free the arena.  NULL is ignored. */
+/* Finish the queued requests, stop the threads and free the arena.  NULL is ignored. */
 void lagp_server_destroy(lagp_server *server);
 
 /* Seconds on the steady (monotonic) clock the server's timestamps use. */

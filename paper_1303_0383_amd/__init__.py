@@ -83,7 +83,9 @@ _lib.lagp_batch_info.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)
 _lib.lagp_batch_destroy.argtypes = [_P]
 _lib.lagp_batch_destroy.restype = None
 _lib.lagp_design_set_variant.argtypes = [_P, C.c_int32, C.c_int32]
+_lib.lagp_design_set_variant_ex.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
 _lib.lagp_server_create.argtypes = [_P, C.c_size_t, C.POINTER(_P)]
+_lib.lagp_server_create_ex.argtypes = [_P, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(_P)]
 _lib.lagp_server_submit.argtypes = [_P, _P, C.c_int32, C.POINTER(lagp_params), _P, _P, C.POINTER(C.c_uint64)]
 _lib.lagp_server_poll.argtypes = [_P, C.c_uint64, C.c_int32, _P, _P, _P, _P, _P, C.c_int64, _P, _P]
 _lib.lagp_server_stats.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -95,8 +97,9 @@ _lib.lagp_last_error.restype = C.c_char_p
 for _f in ("lagp_design_create", "lagp_knn", "lagp_predict", "lagp_workspace_bytes", "lagp_device_count",
            "lagp_version", "lagp_timing_enable", "lagp_phase_times", "lagp_predict_designs", "lagp_batch_create",
            "lagp_batch_enqueue", "lagp_batch_launch_graph", "lagp_batch_info", "lagp_design_set_variant",
-           "lagp_server_create", "lagp_server_submit", "lagp_server_poll", "lagp_server_stats", "lagp_predict_theta",
-           "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex", "lagp_predict_mspe", "lagp_predict_noalloc"):
+           "lagp_design_set_variant_ex",
+           "lagp_server_create", "lagp_server_create_ex", "lagp_server_submit", "lagp_server_poll",
+           "lagp_server_stats", "lagp_predict_theta", "lagp_predict_alc2", "lagp_mle", "lagp_predict_ex", "lagp_predict_mspe", "lagp_predict_noalloc"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -267,9 +270,19 @@ def lagp_design_set_variant(design, threads: int, coords: int) -> None:
     _check(_lib.lagp_design_set_variant(design, threads, coords))
 
 
+def lagp_design_set_variant_ex(design, threads: int, coords: int, lds_rows_pct: int) -> None:
+    _check(_lib.lagp_design_set_variant_ex(design, threads, coords, lds_rows_pct))
+
+
 def lagp_server_create(design, hbm_budget_bytes: int):
     out = _P()
     _check(_lib.lagp_server_create(design, hbm_budget_bytes, C.byref(out)))
+    return out
+
+
+def lagp_server_create_ex(design, hbm_budget_bytes: int, slots: int = 0, piece_locations: int = 0):
+    out = _P()
+    _check(_lib.lagp_server_create_ex(design, hbm_budget_bytes, slots, piece_locations, C.byref(out)))
     return out
 
 
@@ -531,11 +544,12 @@ class Served:
 
 
 class Server:
-    """Owns a lagp_server: continuous batching of host-side requests."""
+    """Owns a lagp_server: continuous batching of host-side requests
+    (slots: pieces in flight, 0 for the default; piece: locations per piece)."""
 
-    def __init__(self, design: Design, hbm_budget_bytes: int):
+    def __init__(self, design: Design, hbm_budget_bytes: int, slots: int = 0, piece: int = 0):
         self.design = design
-        self._h = lagp_server_create(design.handle, int(hbm_budget_bytes))
+        self._h = lagp_server_create_ex(design.handle, int(hbm_budget_bytes), int(slots), int(piece))
         self._n = {}
 
     def close(self):

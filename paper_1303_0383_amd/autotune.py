@@ -2,11 +2,16 @@
 
 For every size class the library buckets locations into -- precision mode x
 candidate-set class (256 .. 4096) x design-size class (32, 64, 128) -- it
-times each kernel variant (workgroup size 256 or 512; candidate coordinates
-in LDS or in global memory) on the GPU with a seeded batch of locations on
-the 8-D sinusoid design, and writes the fastest to a text table:
+times each kernel variant on the GPU with a seeded batch of locations on the
+8-D sinusoid design and writes the fastest to a text table.  A variant is the
+tile shape of one location's workgroup: its size (256 or 512 threads, which
+sets the candidate slots per thread and the tile rows a lane can hold in
+registers), where the candidate coordinates live (LDS or global memory), and
+the share of the remaining LDS given to tile rows (100, 50 or 0 %; rows that
+fit neither registers nor LDS stream from global memory).  Register rows per
+variant are the largest count that compiles without spills.
 
-    <arch> <precision> <ncand class> <n class> <threads> <coords>   # timings
+    <arch> <precision> <ncand class> <n class> <threads> <coords> <lds %>   # timings
 
 The library reads ``tune/table.txt`` next to liblagp.so (or the file named by
 LAGP_TUNE_TABLE) and uses an entry when the device architecture matches;
@@ -30,9 +35,13 @@ MCLASSES = (256, 512, 1024, 2048, 4096)
 NCLASSES = (32, 64, 128)
 
 
+LDS_SHARES = (100, 50, 0)
+
+
 def variants(mclass: int):
+    """(threads, coords, LDS share for tile rows) triples timed for a class."""
     threads = (512,) if mclass > 2048 else (256, 512)
-    return [(t, c) for t in threads for c in (0, 1)]
+    return [(t, c, l) for t in threads for c in (0, 1) for l in LDS_SHARES]
 
 
 def main() -> int:
@@ -53,15 +62,15 @@ def main() -> int:
     XX = torch.as_tensor(w.XX[: args.T], device="cuda:0")
     lines = [f"# greedy-design kernel variants, {args.T} locations of the 8-D sinusoid design "
              f"(d={w.d}, g={w.g}, n0={w.n0}); best of {args.reps} runs, design-phase ms per variant",
-             "# arch precision ncand_class n_class threads coords"]
+             "# arch precision ncand_class n_class threads coords lds_pct"]
     for prec in (L.LAGP_PREC_FP64, L.LAGP_PREC_SCORE_FP32):
         for mc in MCLASSES:
             for nc in NCLASSES:
                 if nc > mc:
                     continue
                 times = {}
-                for (t, c) in variants(mc):
-                    L.lagp_design_set_variant(D.handle, t, c)
+                for (t, c, l) in variants(mc):
+                    L.lagp_design_set_variant_ex(D.handle, t, c, l)
                     D.predict(XX, w.n0, nc, mc, w.d, w.g, precision=prec)   # warm-up
                     torch.cuda.synchronize()
                     best = float("inf")
@@ -73,12 +82,13 @@ def main() -> int:
                         des_ms = L.lagp_phase_times(D.handle)[0]["design"]
                         L.lagp_timing_enable(D.handle, False)
                         best = min(best, des_ms)
-                    times[(t, c)] = best
-                (t, c) = min(times, key=times.get)
-                detail = " ".join(f"{tt}/{'lds' if cc else 'glb'}={ms:.2f}" for (tt, cc), ms in sorted(times.items()))
-                lines.append(f"{arch} {prec} {mc} {nc} {t} {c}   # {detail}")
+                    times[(t, c, l)] = best
+                (t, c, l) = min(times, key=times.get)
+                detail = " ".join(f"{tt}/{'lds' if cc else 'glb'}/{ll}={ms:.2f}"
+                                  for (tt, cc, ll), ms in sorted(times.items()))
+                lines.append(f"{arch} {prec} {mc} {nc} {t} {c} {l}   # {detail}")
                 print(lines[-1], flush=True)
-    L.lagp_design_set_variant(D.handle, 0, -1)
+    L.lagp_design_set_variant_ex(D.handle, 0, -1, -1)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")

@@ -73,11 +73,12 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     const int remA = rows > rregA ? rows - rregA : 0, remB = rows > rregB ? rows - rregB : 0;
     long long costA = -1, costB;
     int rldsA = 0;
+    const int pct = std::max(0, std::min(100, plan->lds_pct));
     if (avail >= pcA * crow_bytes) {
-        rldsA = std::min<long long>(remA, (avail - pcA * crow_bytes) / row_bytes);
+        rldsA = std::min<long long>(remA, (avail - pcA * crow_bytes) / row_bytes * pct / 100);
         costA = global_row_reads(nmax, rregA + rldsA) * (long long)row_bytes;
     }
-    const int rldsB = std::min<long long>(remB, avail / row_bytes);
+    const int rldsB = std::min<long long>(remB, avail / row_bytes * pct / 100);
     costB = (long long)pc * (nmax - 1) * (long long)crow_bytes + global_row_reads(nmax, rregB + rldsB) * (long long)row_bytes;
     bool cl = costA >= 0 && costA <= costB;
     if (plan->coords_pref == 0) cl = false;

@@ -174,7 +174,9 @@ __device__ __forceinline__ double sqdist_lds(const double* __restrict__ a, const
 // multiple of 4 that compiles without scratch spills for P = 8 (a compile
 // sweep), capped at 64 (with one slot per thread LDS holds the rest).  With
 // 256 threads (one wave per SIMD) a lane can hold 512 registers, the upper
-// half as accumulation registers; with 512 threads a lane has 256.
+// half as accumulation registers; with 512 threads a lane has 256.  The
+// mixed mode's short list and re-score leave no room for register rows with
+// 512 threads and 8 slots (with coordinates in LDS it spills a few values).
 __host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = false, bool trim = false)
 {
     if (dt == 256) {
@@ -190,7 +192,7 @@ __host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = 
         case 1: return 64;
         case 2: return 64;
         case 4: return 64;
-        default: return 36;
+        default: return cl ? 28 : 32;
         }
     }
     if (!mix) {
@@ -203,9 +205,9 @@ __host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = 
     }
     switch (cpt) {
     case 1: return 64;
-    case 2: return cl ? 64 : 60;
-    case 4: return cl ? 20 : 24;
-    default: return cl ? 0 : 4;
+    case 2: return 48;
+    case 4: return cl ? 12 : 16;
+    default: return 0;
     }
 }
 

@@ -213,10 +213,11 @@ int size_class(int32_t v, int32_t lo)
     return c;
 }
 
-// ---- tuned kernel variants: text table "arch precision mclass nclass threads coords"
+// ---- tuned kernel variants: text table
+// "arch precision mclass nclass threads coords [lds_pct]"
 struct TuneEntry {
     std::string arch;
-    int prec, mclass, nclass, threads, coords;
+    int prec, mclass, nclass, threads, coords, lds = 100;
 };
 
 std::vector<TuneEntry>& tune_table()
@@ -242,8 +243,11 @@ std::vector<TuneEntry>& tune_table()
             if (line[0] == '#') continue;
             char arch[64];
             TuneEntry t;
-            if (sscanf(line, "%63s %d %d %d %d %d", arch, &t.prec, &t.mclass, &t.nclass, &t.threads, &t.coords) == 6) {
+            const int k = sscanf(line, "%63s %d %d %d %d %d %d", arch, &t.prec, &t.mclass, &t.nclass, &t.threads,
+                                 &t.coords, &t.lds);
+            if (k == 6 || k == 7) {
                 t.arch = arch;
+                if (k == 6 || t.lds < 0 || t.lds > 100) t.lds = 100;
                 table.push_back(t);
             }
         }
@@ -256,9 +260,11 @@ void choose_variant(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, 
 {
     plan->threads = 256;
     plan->coords_pref = -1;
-    if (d->force_threads || d->force_coords >= 0) {
+    plan->lds_pct = 100;
+    if (d->force_threads || d->force_coords >= 0 || d->force_lds_pct >= 0) {
         if (d->force_threads) plan->threads = d->force_threads;
         plan->coords_pref = d->force_coords;
+        if (d->force_lds_pct >= 0) plan->lds_pct = d->force_lds_pct;
         return;
     }
     const int mc = size_class(Mmax, 256), nc = size_class(nmax, 32);
@@ -266,6 +272,7 @@ void choose_variant(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, 
         if (t.arch == d->arch && t.prec == prec && t.mclass == mc && t.nclass == nc) {
             plan->threads = t.threads;
             plan->coords_pref = t.coords;
+            plan->lds_pct = t.lds;
             return;
         }
 }
@@ -1161,6 +1168,16 @@ int lagp_design_set_variant(lagp_design* d, int32_t threads, int32_t coords)
     if (coords < -1 || coords > 1) return fail(LAGP_E_INVAL, "coords must be -1, 0 or 1");
     d->force_threads = threads;
     d->force_coords = coords;
+    d->force_lds_pct = -1;
+    return LAGP_OK;
+}
+
+int lagp_design_set_variant_ex(lagp_design* d, int32_t threads, int32_t coords, int32_t lds_rows_pct)
+{
+    if (lds_rows_pct < -1 || lds_rows_pct > 100) return fail(LAGP_E_INVAL, "lds_rows_pct must be -1 or in [0, 100]");
+    const int rc = lagp_design_set_variant(d, threads, coords);
+    if (rc) return rc;
+    d->force_lds_pct = lds_rows_pct;
     return LAGP_OK;
 }
 

@@ -102,6 +102,7 @@ struct DesignLaunch {
 struct DesignPlan {
     int threads = 0;       // workgroup size (input: 256 or 512 preferred)
     int coords_pref = -1;  // input: -1 traffic model, 0 coordinates in global memory, 1 in LDS when they fit
+    int lds_pct = 100;     // input: percent of the LDS left after the fixed part that holds tile rows
     int p = 0;
     int cpt = 0;           // candidate slots per thread
     int rreg = 0;          // register-resident tile rows

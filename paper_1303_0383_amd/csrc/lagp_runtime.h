@@ -32,6 +32,7 @@ struct lagp_design {
     std::string arch;                   // e.g. "gfx950"
     int force_threads = 0;              // kernel-variant override (0: table or model)
     int force_coords = -1;
+    int force_lds_pct = -1;             // -1: table (else all of the LDS left)
 };
 
 namespace lagp_rt {

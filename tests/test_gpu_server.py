@@ -1,7 +1,8 @@
 """GPU tests of the serving engine (continuous batching under an HBM budget)
 through the C ABI: results against lagp_predict and the FP64 oracle, a
-request alone against the same request mixed into other traffic, admission
-against the budget, and mixed models in one queue."""
+request alone against the same request mixed into other traffic, requests cut
+into pieces, a short request admitted and completed while a long one runs,
+admission against the budget, and mixed models in one queue."""
 import numpy as np
 import pytest
 
@@ -76,10 +77,74 @@ def test_alone_equals_mixed(c4, lagp):
     for t in tickets:
         S.wait(t)
     b1, _, r1, _ = S.stats()
-    print("burst: requests", r1 - r0, "batches", b1 - b0)
+    print("burst: requests", r1 - r0, "pieces", b1 - b0)
     assert r1 - r0 == len(reqs) + 1
     assert b1 - b0 < r1 - r0, "the burst was not batched"
     _served_equals(alone, mixed)
+    S.close()
+
+
+def test_pieces_split_requests(c4, lagp):
+    """Pieces of 7 locations: every request is cut across pieces and pieces
+    hold parts of several requests (one with per-location n and N'); the
+    results equal lagp_predict's bitwise."""
+    X, y, D = c4
+    prm = workloads.C4_PARAMS
+    reqs = workloads.c4_requests(5, 100.0)
+    r = np.random.default_rng(21)
+    xu = r.uniform(0.0, 1.0, (23, 4))
+    nu = r.integers(8, 65, 23).astype(np.int32)
+    mu = r.integers(200, 1500, 23).astype(np.int32)
+    S = lagp.Server(D, 4 * GiB, slots=4, piece=7)
+    tickets = [S.submit(q.XX, prm["n0"], q.n, q.ncand, prm["d"], prm["g"]) for q in reqs]
+    tu = S.submit(xu, prm["n0"], nu, mu, prm["d"], prm["g"])
+    for q, t in zip(reqs, tickets):
+        o = S.wait(t)
+        ref = gpu_predict(D, q.XX, prm["n0"], q.n, q.ncand, prm["d"], prm["g"])
+        for k in ("mean", "s2", "var", "df", "status"):
+            assert np.array_equal(getattr(o, k), ref[k], equal_nan=True), k
+        assert np.array_equal(o.sel, ref["sel"][:, :q.n])
+    o = S.wait(tu)
+    ref = gpu_predict(D, xu, prm["n0"], int(nu.max()), int(mu.max()), prm["d"], prm["g"], n_per=nu, M_per=mu)
+    for k in ("mean", "s2", "var", "df", "status"):
+        assert np.array_equal(getattr(o, k), ref[k], equal_nan=True), k
+    for t in range(len(xu)):
+        assert np.array_equal(o.sel[t, :nu[t]], ref["sel"][t, :nu[t]])
+    pieces, locs, nreq, _ = S.stats()
+    total = sum(len(q.XX) for q in reqs) + len(xu)
+    assert locs == total and nreq == len(reqs) + 1
+    assert pieces >= -(-total // 7)
+    S.close()
+
+
+def test_short_request_overtakes_long_work(c4, lagp):
+    """Continuous batching: a one-location request submitted while a long
+    request (16384 locations, n = 100, N' = 4000) is on the device is admitted
+    at once, runs beside it and completes first, at its own completion time;
+    both give lagp_predict's results bitwise."""
+    import time
+    X, y, D = c4
+    prm = workloads.C4_PARAMS
+    r = np.random.default_rng(11)
+    big = r.uniform(0.0, 1.0, (16384, 4))
+    small = r.uniform(0.0, 1.0, (1, 4))
+    S = lagp.Server(D, 16 * GiB)
+    tb = S.submit(big, prm["n0"], 100, 4000, prm["d"], prm["g"])
+    time.sleep(0.05)
+    ts = S.submit(small, prm["n0"], 32, 1000, prm["d"], prm["g"])
+    o_s = S.wait(ts)
+    o_b = S.wait(tb)
+    print(f"long: {1e3 * (o_b.done - o_b.submitted):.1f} ms; short: submitted "
+          f"{1e3 * (o_s.submitted - o_b.submitted):.1f} ms later, served in {1e3 * (o_s.done - o_s.submitted):.1f} ms")
+    assert o_b.submitted < o_s.submitted and o_s.done < o_b.done
+    pieces, _, _, _ = S.stats()
+    assert pieces >= 16384 // 4096 + 1
+    ref = gpu_predict(D, small, prm["n0"], 32, 1000, prm["d"], prm["g"])
+    assert np.array_equal(o_s.mean, ref["mean"]) and np.array_equal(o_s.sel, ref["sel"][:, :32])
+    ref = gpu_predict(D, big, prm["n0"], 100, 4000, prm["d"], prm["g"])
+    for k in ("mean", "s2", "var", "df", "status"):
+        assert np.array_equal(getattr(o_b, k), ref[k], equal_nan=True), k
+    assert np.array_equal(o_b.sel, ref["sel"][:, :100])
     S.close()
 
 
@@ -144,3 +209,6 @@ def test_server_invalid_requests(c4, lagp):
     S.close()
     with pytest.raises(E):
         lagp.lagp_server_create(D.handle, 1000)                      # budget below 1 MiB
+    for slots, piece in ((1, 0), (9, 0), (0, -1), (0, 1 << 18)):     # slot count, piece size
+        with pytest.raises(E):
+            lagp.lagp_server_create_ex(D.handle, 1 * GiB, slots, piece)
