@@ -322,8 +322,9 @@ def main() -> int:
     else:
         alg_bytes = T * design_alg_bytes(w.n, w.ncand, w.p)
     kname = "mspe_kernel" if mspe else "design_kernel"
-    # counter files hold the FP64 one-stage kernel's traffic for a workload
-    traffic = read_traffic(kname, args.workload) if (args.precision == "fp64" and not alc2) else None
+    # counter files hold the one-stage kernel's traffic for a workload and precision
+    tag = args.workload + ("" if args.precision == "fp64" else "_fp32")
+    traffic = read_traffic(kname, tag) if not alc2 else None
     roofline = roofline_entry(kname, per_launch_flops, passes * alg_bytes / launches_per_step, traffic, avg_launch_s)
     roofline.update(launches_per_step=launches_per_step, exps_per_launch=exps / launches_per_step,
                     exp_rate_G_per_s=round(exps / launches_per_step / avg_launch_s / 1e9, 2))
