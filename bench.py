@@ -178,7 +178,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2_n50", choices=["c2_n50", "c2", "c1", "c0", "c3", "c4"])
     ap.add_argument("--T", type=int, default=None, help="use only the first T locations")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="ranking tile: fp64, or fp32 / bf16 with the exact FP64 short-list re-score")
     ap.add_argument("--method", default="alc", choices=["alc", "alc2", "mspe"],
                     help="alc: designs at the fixed lengthscale; alc2: the two-stage scheme with local MLEs; "
                          "mspe: greedy designs by the MSPE criterion")
@@ -221,7 +222,8 @@ def main() -> int:
         return serve_bench(args, lagp, torch)
     dev = torch.device("cuda:0")
     w = workload(args.workload, args.T)
-    prec = lagp.LAGP_PREC_FP64 if args.precision == "fp64" else lagp.LAGP_PREC_SCORE_FP32
+    prec = {"fp64": lagp.LAGP_PREC_FP64, "fp32": lagp.LAGP_PREC_SCORE_FP32,
+            "bf16": lagp.LAGP_PREC_SCORE_BF16}[args.precision]
     D = lagp.Design(w.X, w.y)
     XX = torch.as_tensor(w.XX, device=dev)
     n_per = None if w.n_per is None else torch.as_tensor(w.n_per, device=dev)
@@ -323,7 +325,7 @@ def main() -> int:
         alg_bytes = T * design_alg_bytes(w.n, w.ncand, w.p)
     kname = "mspe_kernel" if mspe else "design_kernel"
     # counter files hold the one-stage kernel's traffic for a workload and precision
-    tag = args.workload + ("" if args.precision == "fp64" else "_fp32")
+    tag = args.workload + ("" if args.precision == "fp64" else "_" + args.precision)
     traffic = read_traffic(kname, tag) if not alc2 else None
     roofline = roofline_entry(kname, per_launch_flops, passes * alg_bytes / launches_per_step, traffic, avg_launch_s)
     roofline.update(launches_per_step=launches_per_step, exps_per_launch=exps / launches_per_step,
@@ -343,7 +345,8 @@ def main() -> int:
         "metric": METRIC, "value": round(value, 1), "unit": "locations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32-tile", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f64+f32-tile", "bf16": "f64+bf16-tile"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": args.workload, "method": args.method, "N": w.N, "p": w.p, "T": T, "n0": w.n0,
                    "n": nmax, "ncand": Mmax, "d": w.d, "g": w.g, "uneven": w.n_per is not None, "graph": use_graph},
         "phase_ms_per_step": {k: round(v / args.steps, 3) for k, v in phase.items() if v > 0 or k in ("knn", "design")},
@@ -382,7 +385,7 @@ def main() -> int:
     rng = np.random.default_rng(20130383)
 
     # Parity of sampled outputs against the FP64 oracle.
-    if args.parity_sample > 0 and args.precision == "fp32":
+    if args.parity_sample > 0 and args.precision != "fp64":
         # Mixed precision: per-step agreement under replay, sequence identity,
         # mean RMS difference from the FP64 oracle over sd(y), and the FP64
         # prediction from the chosen indices against the oracle's.

@@ -63,16 +63,25 @@ enum { LAGP_LOC_OK = 0, LAGP_LOC_NOTPD = 1, LAGP_LOC_NOTCAND = 2 /* a saved star
        LAGP_LOC_NOCAND = 3 /* the candidate set could not be formed (a kNN consistency check failed; calls
                               that wait on the host return an error instead) */ };
 
-/* Precision of the ALC scoring contraction.  The variance v_j(c), covariance
- * cov_j(x,c), the factor update and the final prediction are FP64 in every
- * mode. */
+/* Precision of the ALC scoring contraction (eq dxy2 over the whitened tile
+ * of the partitioned-inverse step, Supplementary Material Section 1).  The
+ * factor of the chosen points, the chosen point's score and the prediction
+ * are FP64 in every mode. */
 typedef enum {
     LAGP_PREC_FP64 = 0,        /* everything FP64; the prediction reuses the greedy factor */
-    LAGP_PREC_SCORE_FP32 = 1   /* ranking tile stored and contracted in FP32; K(s,c), v, cov,
-                                  the update and the argmax FP64; the prediction refactorises
-                                  K_n in FP64 from the chosen indices (n <= ~190); a location
-                                  whose FP32 ranking loses positive definiteness is redone
-                                  entirely in FP64 on the device */
+    LAGP_PREC_SCORE_FP32 = 1,  /* ranking tile stored and contracted in FP32 (v and cov
+                                  accumulated in FP64); every step re-scores the FP32 ranking's
+                                  best candidates exactly in FP64 -- each one's column of the
+                                  whitened tile by forward substitution against the exact FP64
+                                  factor -- and takes the exact argmax; the factor grows by the
+                                  exact row and the prediction is FP64 from it (n <= 128).  Where
+                                  the FP64 argmax is among the re-scored candidates, the design
+                                  and outputs are bitwise those of LAGP_PREC_FP64.  A location
+                                  whose short list holds no candidate with a positive exact
+                                  variance is redone entirely in FP64 on the device */
+    LAGP_PREC_SCORE_BF16 = 2   /* as LAGP_PREC_SCORE_FP32 with the ranking tile stored as
+                                  bfloat16 (rounded to nearest even) and contracted with FP32
+                                  accumulation: half the tile bytes, a coarser ranking */
 } lagp_precision;
 
 /* Flags. */

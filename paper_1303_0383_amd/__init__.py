@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_PKG, "liblagp.so")
 
 LAGP_OK, LAGP_E_INVAL, LAGP_E_NOMEM, LAGP_E_NODEVICE, LAGP_E_HIP, LAGP_E_BUDGET, LAGP_E_NOTPD = 0, -1, -2, -3, -4, -5, -6
 LAGP_LOC_OK, LAGP_LOC_NOTPD, LAGP_LOC_NOTCAND, LAGP_LOC_NOCAND = 0, 1, 2, 3
-LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32 = 0, 1
+LAGP_PREC_FP64, LAGP_PREC_SCORE_FP32, LAGP_PREC_SCORE_BF16 = 0, 1, 2
 LAGP_PTR_HOST, LAGP_STRICT = 1, 2
 LAGP_BATCH_SEL, LAGP_BATCH_STATUS = 1, 2
 PHASES = ("knn", "design", "mle", "predict")   # LAGP_PHASE_* order

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblagp.so")
 SOURCES = ["lagp_api.cpp", "server.cpp", "knn.hip", "design.hip", "design_f64.hip", "design_f64_trim.hip", "design_mix.hip",
-           "design_mix_trim.hip", "predict.hip", "mle.hip", "mspe.hip", "noalloc.hip"]
+           "design_mix_trim.hip", "design_bf16.hip", "design_bf16_trim.hip", "predict.hip", "mle.hip", "mspe.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

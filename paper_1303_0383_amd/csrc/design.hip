@@ -12,6 +12,7 @@ namespace lagp {
 
 static int launch_any(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
+    if (plan.bf16) return plan.trim ? design_launch_bf16_trim(a, plan, stream, err) : design_launch_bf16(a, plan, stream, err);
     if (plan.mix) return plan.trim ? design_launch_mix_trim(a, plan, stream, err) : design_launch_mix(a, plan, stream, err);
     return plan.trim ? design_launch_f64_trim(a, plan, stream, err) : design_launch_f64(a, plan, stream, err);
 }
@@ -48,7 +49,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
                 int num_cu, size_t max_lds, DesignPlan* plan, std::string* err)
 {
     (void)n0;
-    const bool mix = precision != 0;
+    const bool mix = precision != 0, bf16 = precision == 2;
     int dt = plan->threads == 512 ? 512 : 256;
     if (Mmax > 2048) dt = 512;   // at most 8 slots per thread
     int cpt = 1;
@@ -60,7 +61,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     if (mix && nmax > 128) { *err = "the mixed precision mode supports n <= 128"; return -1; }
     const size_t fixed = fixed_lds_bytes(nmax, p, dt, mix);
     if (fixed > max_lds) { *err = "local design size too large for LDS"; return -1; }
-    const size_t row_bytes = (size_t)Mpad * (mix ? sizeof(float) : sizeof(double));   // tile row
+    const size_t row_bytes = (size_t)Mpad * (bf16 ? 2 : mix ? sizeof(float) : sizeof(double));   // tile row
     const size_t crow_bytes = (size_t)Mpad * sizeof(double);                          // coordinate row
     const size_t avail = max_lds - fixed;
     // Option A: coordinates in LDS.  Option B: coordinates in global memory.
@@ -89,6 +90,7 @@ int design_plan(const DeviceDesign& D, int32_t nmax, int32_t Mmax, int32_t Mmin,
     plan->lds_limit = max_lds;
     plan->trim = trim;
     plan->mix = mix;
+    plan->bf16 = bf16;
     plan->rreg = cl ? rregA : rregB;
     plan->rlds = cl ? rldsA : rldsB;
     plan->rglob = (cl ? remA : remB) - plan->rlds;

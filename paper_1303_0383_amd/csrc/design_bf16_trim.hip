@@ -1,0 +1,12 @@
+// design_bf16_trim.hip -- greedy-design kernel variants with a BF16 tile, TRIM=true
+// (one translation unit per pair so that the variants compile in parallel).
+#include "design_kernel.h"
+
+namespace lagp {
+
+int design_launch_bf16_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
+{
+    return launch_variant<2, true>(a, plan, stream, err);
+}
+
+}  // namespace lagp

@@ -1,4 +1,4 @@
-// design_f64_trim.hip -- greedy-design kernel variants with MIX=false, TRIM=true
+// design_f64_trim.hip -- greedy-design kernel variants with an FP64 tile, TRIM=true
 // (one translation unit per pair so that the variants compile in parallel).
 #include "design_kernel.h"
 
@@ -6,7 +6,7 @@ namespace lagp {
 
 int design_launch_f64_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    return launch_variant<false, true>(a, plan, stream, err);
+    return launch_variant<0, true>(a, plan, stream, err);
 }
 
 }  // namespace lagp

@@ -304,6 +304,40 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int voff, int s
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
 }
 
+// Tile storage: the FP64 and FP32 tiles keep rows in their compute type; the
+// BF16 tile stores rows as bfloat16 (round to nearest even) and computes in
+// FP32, so a row's register, LDS and global copies hold the same value.
+template <int MIX>
+struct TileTypes {
+    using W = typename std::conditional<MIX != 0, float, double>::type;   // compute
+    using S = typename std::conditional<MIX == 2, __bf16, W>::type;       // LDS and global rows
+};
+
+template <int MIX>
+__device__ __forceinline__ typename TileTypes<MIX>::W tile_round(double r)
+{
+    if constexpr (MIX == 2) return (float)(__bf16)(float)r;
+    else return (typename TileTypes<MIX>::W)r;
+}
+
+template <int MIX>
+__device__ __forceinline__ void bload_tile(__amdgpu_buffer_rsrc_t r, int voff, int soff, typename TileTypes<MIX>::W& v)
+{
+    if constexpr (MIX == 2)
+        v = (float)__builtin_bit_cast(__bf16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    else
+        bload(r, voff, soff, v);
+}
+
+template <int MIX>
+__device__ __forceinline__ void bstore_tile(__amdgpu_buffer_rsrc_t r, int voff, int soff, typename TileTypes<MIX>::W v)
+{
+    if constexpr (MIX == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, voff, soff, 0);
+    else
+        bstore(r, voff, soff, v);
+}
+
 // Squared distance from the uniform point a to the candidate whose P
 // coordinates sit in the slab at byte offsets soff + k * cstride (+ voff).
 template <int P>
@@ -340,10 +374,11 @@ __device__ __forceinline__ void ld4(const float* p, float* o)
 // compiler from hoisting every slot's coordinate loads at once), LDS rows are
 // consumed one at a time, and the global rows stream through a ring of three
 // row buffers (two rows in flight while one is consumed).
-template <int DT, int CPT, int RREG, int P, bool CL, bool MIX, bool TRIM>
+template <int DT, int CPT, int RREG, int P, bool CL, int MIX, bool TRIM>
 __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 {
-    using TW = typename std::conditional<MIX, float, double>::type;
+    using TW = typename TileTypes<MIX>::W;   // tile compute type
+    using TS = typename TileTypes<MIX>::S;   // LDS and global tile rows
     constexpr int DWAVES = DT / 64;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
@@ -388,19 +423,19 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
     if (MIX) off = (((size_t)((char*)(mxi + 2 * DWAVES) - (char*)smem)) + 15) & ~(size_t)15;
     const int ylds = CL ? A.y_lds : 0;
     double* Xcl = (double*)((char*)smem + off);              // [p (+1)][Mpad] when CL: coordinates (y)
-    TW* Wl = (TW*)(Xcl + (CL ? (size_t)(p + ylds) * Mpad : 0));  // [rlds][Mpad]
+    TS* Wl = (TS*)(Xcl + (CL ? (size_t)(p + ylds) * Mpad : 0));  // [rlds][Mpad]
 
     double* Xcg = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-    TW* Wg = (TW*)(Xcg + (CL ? 0 : (int64_t)p * Mpad));
+    TS* Wg = (TS*)(Xcg + (CL ? 0 : (int64_t)p * Mpad));
     double* Xc = CL ? Xcl : Xcg;
     const __amdgpu_buffer_rsrc_t slab = slab_rsrc(Xcg, (uint32_t)(A.scratch_stride * sizeof(double)));
     const int voff_c = tid * (int)sizeof(double);     // coordinate element of slot k = 0
-    const int voff_w = tid * (int)sizeof(TW);         // tile-row element of slot k = 0
+    const int voff_w = tid * (int)sizeof(TS);         // tile-row element of slot k = 0
     const int wbase = CL ? 0 : p * Mpad * (int)sizeof(double);   // tile rows after the coordinates
-    const int rowb = Mpad * (int)sizeof(TW);                      // bytes per global tile row
+    const int rowb = Mpad * (int)sizeof(TS);                      // bytes per global tile row
     const int rlds = A.rlds;
     const int G0 = RREG + rlds;   // first global row
-    for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = 0.0;
+    for (int e = tid; e < rlds * Mpad; e += DT) Wl[e] = (TS)0.0f;
     (void)xsl;
 
     for (;;) {
@@ -583,7 +618,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 chosen |= 1u << kk;
             }
             for (int l = RREG + tid; l < i; l += DT)
-                ws[l] = (l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s];
+                ws[l] = (TW)((l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s]);
             // one response per step: from LDS when it holds them, else from the design
             const double ys = (CL && ylds) ? Xc[(int64_t)p * Mpad + s] : A.y[cand[s]];
             double ax, acc[CPT];
@@ -642,7 +677,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 const int rb = wbase + (l - G0) * rowb;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k)
-                    bload(slab, voff_w, rb + (full ? k * DT : (k < kact ? k : kact - 1) * DT) * (int)sizeof(TW), b[k]);
+                    bload_tile<MIX>(slab, voff_w, rb + (full ? k * DT : (k < kact ? k : kact - 1) * DT) * (int)sizeof(TS), b[k]);
             };
             if (gcount > 0) {
 #pragma unroll
@@ -694,14 +729,14 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 const int le = i < G0 ? i : G0;
                 for (int l = RREG; l < le; ++l) {
                     const TW wl = ws[l];
-                    const TW* row = Wl + (int64_t)(l - RREG) * Mpad + tid;
+                    const TS* row = Wl + (int64_t)(l - RREG) * Mpad + tid;
                     if constexpr (MIX) {
 #pragma unroll
-                        for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wl, row[k * DT], dot[k]);
+                        for (int k = 0; k < CPT; ++k) dot[k] = __builtin_fmaf(wl, (float)row[k * DT], dot[k]);
                         dotx = __builtin_fmaf(wl, wx[l], dotx);
                     } else {
 #pragma unroll
-                        for (int k = 0; k < CPT; ++k) acc[k] -= wl * row[k * DT];
+                        for (int k = 0; k < CPT; ++k) acc[k] -= wl * (TW)row[k * DT];
                         ax -= wl * wx[l];
                         ay -= wl * uu[l];
                     }
@@ -764,17 +799,17 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
                     if (l == i) {
 #pragma unroll
-                        for (int k = 0; k < CPT; ++k) Wr[l][k] = (TW)r[k];
+                        for (int k = 0; k < CPT; ++k) Wr[l][k] = tile_round<MIX>(r[k]);
                     }
             } else if (i < G0) {
-                TW* row = Wl + (int64_t)(i - RREG) * Mpad + tid;
+                TS* row = Wl + (int64_t)(i - RREG) * Mpad + tid;
 #pragma unroll
-                for (int k = 0; k < CPT; ++k) row[k * DT] = (TW)r[k];
+                for (int k = 0; k < CPT; ++k) row[k * DT] = (TS)tile_round<MIX>(r[k]);
             } else {
                 const int rb = wbase + (i - G0) * rowb;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k)
-                    if (full || k < kact) bstore(slab, voff_w, rb + k * DT * (int)sizeof(TW), (TW)r[k]);
+                    if (full || k < kact) bstore_tile<MIX>(slab, voff_w, rb + k * DT * (int)sizeof(TS), tile_round<MIX>(r[k]));
             }
 
             // Argmax of ALC_{i+1} over live candidates (needed from step n0 on).
@@ -1034,7 +1069,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     }
                 }
                 for (int l = RREG + tid; l < i; l += DT)
-                    ws[l] = (l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s];
+                    ws[l] = (TW)((l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s]);
                 __syncthreads();
                 const double vs = misc[0];
                 if (!(vs > 0.0)) {
@@ -1093,7 +1128,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 
 // With `a` null the kernel variant's dynamic-LDS limit is raised (host-side
 // set-up, kept out of stream capture); otherwise the kernel is launched.
-template <int DT, int CPT, int P, bool CL, bool MIX, bool TRIM>
+template <int DT, int CPT, int P, bool CL, int MIX, bool TRIM>
 static int launch_design(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     constexpr int RREG = rreg_for(DT, CPT, CL, MIX, TRIM);
@@ -1112,7 +1147,7 @@ static int launch_design(const DesignArgs* a, const DesignPlan& plan, hipStream_
     return 0;
 }
 
-template <int DT, int CPT, bool CL, bool MIX, bool TRIM>
+template <int DT, int CPT, bool CL, int MIX, bool TRIM>
 static int launch_design_p(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     switch (plan.p) {
@@ -1123,14 +1158,14 @@ static int launch_design_p(const DesignArgs* a, const DesignPlan& plan, hipStrea
     }
 }
 
-template <int DT, int CPT, bool MIX, bool TRIM>
+template <int DT, int CPT, int MIX, bool TRIM>
 static int launch_design_c(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     return plan.coords_lds ? launch_design_p<DT, CPT, true, MIX, TRIM>(a, plan, stream, err)
                            : launch_design_p<DT, CPT, false, MIX, TRIM>(a, plan, stream, err);
 }
 
-template <int DT, bool MIX, bool TRIM>
+template <int DT, int MIX, bool TRIM>
 static int launch_design_dt(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     switch (plan.cpt) {
@@ -1142,8 +1177,8 @@ static int launch_design_dt(const DesignArgs* a, const DesignPlan& plan, hipStre
     }
 }
 
-// One translation unit per (MIX, TRIM) pair instantiates its variants.
-template <bool MIX, bool TRIM>
+// One translation unit per (tile precision, TRIM) pair instantiates its variants.
+template <int MIX, bool TRIM>
 static int launch_variant(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
     return plan.threads == 256 ? launch_design_dt<256, MIX, TRIM>(a, plan, stream, err)
@@ -1154,5 +1189,7 @@ int design_launch_f64(const DesignArgs* a, const DesignPlan& plan, hipStream_t s
 int design_launch_f64_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err);
 int design_launch_mix(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err);
 int design_launch_mix_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err);
+int design_launch_bf16(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err);
+int design_launch_bf16_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err);
 
 }  // namespace lagp

@@ -1,4 +1,4 @@
-// design_mix_trim.hip -- greedy-design kernel variants with MIX=true, TRIM=true
+// design_mix_trim.hip -- greedy-design kernel variants with an FP32 tile, TRIM=true
 // (one translation unit per pair so that the variants compile in parallel).
 #include "design_kernel.h"
 
@@ -6,7 +6,7 @@ namespace lagp {
 
 int design_launch_mix_trim(const DesignArgs* a, const DesignPlan& plan, hipStream_t stream, std::string* err)
 {
-    return launch_variant<true, true>(a, plan, stream, err);
+    return launch_variant<1, true>(a, plan, stream, err);
 }
 
 }  // namespace lagp

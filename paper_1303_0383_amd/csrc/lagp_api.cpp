@@ -268,13 +268,15 @@ void choose_variant(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, 
         return;
     }
     const int mc = size_class(Mmax, 256), nc = size_class(nmax, 32);
-    for (const TuneEntry& t : tune_table())
-        if (t.arch == d->arch && t.prec == prec && t.mclass == mc && t.nclass == nc) {
-            plan->threads = t.threads;
-            plan->coords_pref = t.coords;
-            plan->lds_pct = t.lds;
-            return;
-        }
+    // a BF16-tile class without its own entry takes the FP32 tile's
+    for (const int pr : {prec, prec == LAGP_PREC_SCORE_BF16 ? (int)LAGP_PREC_SCORE_FP32 : prec})
+        for (const TuneEntry& t : tune_table())
+            if (t.arch == d->arch && t.prec == pr && t.mclass == mc && t.nclass == nc) {
+                plan->threads = t.threads;
+                plan->coords_pref = t.coords;
+                plan->lds_pct = t.lds;
+                return;
+            }
 }
 
 int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int32_t Mmin, int32_t n0, int64_t count,
@@ -298,7 +300,8 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
     const int64_t N = d->dev.N;
     if (!(prm->d > 0.0) || !isfinite(prm->d)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
     if (!(prm->g >= 0.0) || !isfinite(prm->g)) return fail(LAGP_E_INVAL, "nugget g must be >= 0 and finite");
-    if (prm->precision != LAGP_PREC_FP64 && prm->precision != LAGP_PREC_SCORE_FP32)
+    if (prm->precision != LAGP_PREC_FP64 && prm->precision != LAGP_PREC_SCORE_FP32 &&
+        prm->precision != LAGP_PREC_SCORE_BF16)
         return fail(LAGP_E_INVAL, "unsupported precision mode");
     if (prm->flags & ~(uint32_t)LAGP_STRICT) return fail(LAGP_E_INVAL, "unknown flag");
     if (prm->n0 < 1) return fail(LAGP_E_INVAL, "n0 must be >= 1");
@@ -308,7 +311,7 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
     P->prm = *prm;
     P->T = T;
     P->uneven = hn || hm;
-    P->mix = prm->precision == LAGP_PREC_SCORE_FP32;
+    P->mix = prm->precision != LAGP_PREC_FP64;
     int32_t nmax = prm->n, Mmax = prm->ncand;
     P->nmin = hn ? INT32_MAX : prm->n;
     if (P->uneven) {

@@ -116,7 +116,8 @@ struct DesignPlan {
     size_t scratch_per_block = 0;  // bytes of global scratch per block
     size_t counter_bytes = 0;
     long long global_row_reads = 0;  // modelled candidate-row reads from global memory per location
-    bool mix = false;                // FP32 tile
+    bool mix = false;                // FP32 or BF16 ranking tile with an exact re-score
+    bool bf16 = false;               // BF16 tile storage
     bool trim = false;               // variant that skips empty slot columns
 };
 
