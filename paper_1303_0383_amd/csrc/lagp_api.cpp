@@ -159,6 +159,11 @@ void lagp_design_destroy(lagp_design* d)
     if (!d) return;
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+    for (int l = 0; l + 1 < lagp_design::kLanes; ++l) {
+        if (d->lane_stream[l]) (void)hipStreamDestroy(d->lane_stream[l]);
+        if (d->lane_join[l]) (void)hipEventDestroy(d->lane_join[l]);
+    }
+    if (d->lane_fork) (void)hipEventDestroy(d->lane_fork);
     if (d->Xaos) (void)hipFree(d->Xaos);
     if (d->Xaos_s) (void)hipFree(d->Xaos_s);
     if (d->y) (void)hipFree(d->y);
@@ -293,9 +298,12 @@ int plan_design(const lagp_design* d, int prec, int32_t nmax, int32_t Mmax, int3
 
 // Checks parameters and per-location sizes (host arrays, nullable) and builds the plan.
 int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
-               bool have_sel, bool have_status, Plan* P, int64_t chunk)
+               bool have_sel, bool have_status, Plan* P, int64_t chunk, int lanes)
 {
     if (chunk < 1) return fail(LAGP_E_INVAL, "chunk must be >= 1");
+    if (const char* e = getenv("LAGP_BUCKET_LANES")) lanes = std::min(lanes, atoi(e));   // measurement override
+    lanes = std::max(1, std::min(lanes, (int)lagp_design::kLanes));
+    int max_lanes = 1;
     P->chunk = chunk;
     const int64_t N = d->dev.N;
     if (!(prm->d > 0.0) || !isfinite(prm->d)) return fail(LAGP_E_INVAL, "lengthscale d must be positive and finite");
@@ -395,6 +403,19 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
             if (rc) return rc;
             design_b = std::max(design_b, lagp::design_workspace_bytes(b.plan));
         }
+        // Concurrent lanes: each bucket (largest classes first) joins the lane
+        // with the least estimated work so far (count x n^2 x N'), so one
+        // bucket's tail overlaps the others' work.
+        c.lanes = (int)std::min<size_t>((size_t)lanes, c.buckets.size());
+        std::vector<double> load(c.lanes, 0.0);
+        for (Bucket& b : c.buckets) {
+            int best = 0;
+            for (int l = 1; l < c.lanes; ++l)
+                if (load[l] < load[best]) best = l;
+            b.lane = best;
+            load[best] += (double)b.count * b.nmax * b.nmax * b.Mmax;
+        }
+        max_lanes = std::max(max_lanes, c.lanes);
         if (P->mix) {
             int rc = plan_design(d, LAGP_PREC_FP64, c.nmax, c.Mmax, c.Mmin, prm->n0, c.T, &c.redo);
             if (rc) return rc;
@@ -404,7 +425,8 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
     }
     P->knn_b = lagp::align256(lagp::knn_workspace_bytes(tc_max, lagp::KNN_BUCKET_MAX));
     P->cand_b = lagp::align256((size_t)tc_max * Mmax * sizeof(int32_t));
-    P->design_b = lagp::align256(design_b);
+    P->lane_b = lagp::align256(design_b);
+    P->design_b = P->lane_b * max_lanes;
     P->order_b = P->uneven ? lagp::align256((size_t)T * sizeof(int32_t)) : 0;
     P->sel_b = P->own_sel ? lagp::align256((size_t)tc_max * nmax * sizeof(int32_t)) : 0;
     P->status_b = P->own_status ? lagp::align256((size_t)T) : 0;
@@ -423,9 +445,22 @@ int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const in
 }
 
 // Host-side kernel set-up for every variant the plan launches.
-int prepare_plan(const lagp_design* d, const Plan& P)
+int prepare_plan(const lagp_design* dc, const Plan& P)
 {
     std::string err;
+    lagp_design* d = const_cast<lagp_design*>(dc);
+    bool lanes = false;
+    for (const Chunk& c : P.chunks) lanes = lanes || c.lanes > 1;
+    if (lanes) {
+        std::lock_guard<std::mutex> lk(d->lane_mu);
+        hipError_t e = hipSuccess;
+        if (!d->lane_fork) e = hipEventCreateWithFlags(&d->lane_fork, hipEventDisableTiming);
+        for (int l = 0; l + 1 < lagp_design::kLanes && e == hipSuccess; ++l) {
+            if (!d->lane_stream[l]) e = hipStreamCreateWithFlags(&d->lane_stream[l], hipStreamNonBlocking);
+            if (e == hipSuccess && !d->lane_join[l]) e = hipEventCreateWithFlags(&d->lane_join[l], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) return hip_fail("bucket lane streams", e);
+    }
     if (lagp::knn_prepare(d->dev.p, d->max_lds, &err)) return fail(LAGP_E_HIP, err);
     for (const Chunk& c : P.chunks) {
         for (const Bucket& b : c.buckets)
@@ -484,14 +519,37 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
                            hipStream_t s)
 {
     std::string err;
+    // Buckets in several lanes: the lanes' streams wait for the caller's
+    // stream, each lane runs its buckets in order in its own workspace, and
+    // the caller's stream waits for every lane (in stream capture these are
+    // the graph's fork and join).
+    const bool fork = c.lanes > 1;
+    std::unique_lock<std::mutex> lk(d->lane_mu, std::defer_lock);
+    if (fork) {
+        lk.lock();
+        hipError_t e = hipEventRecord(d->lane_fork, s);
+        for (int l = 1; l < c.lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(d->lane_stream[l - 1], d->lane_fork, 0);
+        if (e != hipSuccess) return hip_fail("bucket lanes: fork", e);
+    }
     for (const Bucket& b : c.buckets) {
         L.precision = P.prm.precision;
         L.T = b.count;
         L.n = b.nmax;
         L.M = b.Mmax;
         L.order = order_dev ? order_dev + c.t0 + b.first : nullptr;
-        int r = lagp::design_run(d->dev, L, b.plan, des_ws, P.design_b, s, &err);
+        hipStream_t ls = b.lane == 0 ? s : d->lane_stream[b.lane - 1];
+        void* ws = (char*)des_ws + (size_t)b.lane * P.lane_b;
+        int r = lagp::design_run(d->dev, L, b.plan, ws, P.lane_b, ls, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+    }
+    if (fork) {
+        hipError_t e = hipSuccess;
+        for (int l = 1; l < c.lanes && e == hipSuccess; ++l) {
+            e = hipEventRecord(d->lane_join[l - 1], d->lane_stream[l - 1]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, d->lane_join[l - 1], 0);
+        }
+        if (e != hipSuccess) return hip_fail("bucket lanes: join", e);
+        lk.unlock();
     }
     if (P.mix) {
         // A location the mixed mode could not finish (its short list held no
@@ -507,7 +565,7 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
         L.M = c.Mmax;
         L.order = redo_list;
         L.count = redo_count;
-        r = lagp::design_run(d->dev, L, c.redo, des_ws, P.design_b, s, &err);
+        r = lagp::design_run(d->dev, L, c.redo, des_ws, P.lane_b, s, &err);
         if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     }
     return LAGP_OK;

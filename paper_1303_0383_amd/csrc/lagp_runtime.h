@@ -6,6 +6,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,14 @@ struct lagp_design {
     int force_threads = 0;              // kernel-variant override (0: table or model)
     int force_coords = -1;
     int force_lds_pct = -1;             // -1: table (else all of the LDS left)
+    // Streams and events that run the size buckets of an uneven plan in
+    // concurrent lanes (lane 0 is the caller's stream); created outside
+    // capture by prepare_plan, guarded by lane_mu while a plan forks.
+    static constexpr int kLanes = 3;
+    hipStream_t lane_stream[kLanes - 1] = {};
+    hipEvent_t lane_fork = nullptr;
+    hipEvent_t lane_join[kLanes - 1] = {};
+    std::mutex lane_mu;
 };
 
 namespace lagp_rt {
@@ -48,12 +57,14 @@ struct Bucket {
     int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
     int64_t first = 0, count = 0;   // range of the chunk's work list
     lagp::DesignPlan plan;
+    int lane = 0;                   // concurrent lane (stream) the bucket runs in
 };
 
 struct Chunk {
     int64_t t0 = 0, T = 0;
     int32_t nmax = 0, Mmax = 0, Mmin = 1 << 30;
     std::vector<Bucket> buckets;
+    int lanes = 1;                  // lanes in use (1: every bucket on the caller's stream)
     lagp::DesignPlan redo;   // FP64 plan for locations the mixed mode could not finish
 };
 
@@ -70,6 +81,7 @@ struct Plan {
     std::vector<int32_t> order;   // chunk-relative locations, chunk c at [t0, t0 + T)
     // workspace layout
     size_t knn_b = 0, cand_b = 0, design_b = 0, order_b = 0, sel_b = 0, status_b = 0, redo_b = 0;
+    size_t lane_b = 0;            // design workspace per lane (design_b = lanes x lane_b)
     size_t sel1_b = 0, stage_b = 0;   // two-stage: first designs; stage outputs and lengthscales
     size_t total = 0;
 };
@@ -98,8 +110,10 @@ struct Outputs {
 // Checks parameters and per-location sizes (host arrays, nullable) and builds
 // the plan for T locations.
 // `chunk` bounds the locations per launch sequence (and so the workspace).
+// `lanes` bounds the concurrent lanes of an uneven plan's size buckets.
 int build_plan(const lagp_design* d, const lagp_params* prm, int64_t T, const int32_t* hn, const int32_t* hm,
-               bool have_sel, bool have_status, Plan* P, int64_t chunk = kChunk);
+               bool have_sel, bool have_status, Plan* P, int64_t chunk = kChunk,
+               int lanes = lagp_design::kLanes);
 // Turns a plan into the two-stage scheme: checks the search controls and
 // n >= 2, and adds the stage workspace.  have_sel: the caller passes sel.
 int plan_alc2(const lagp_design* d, const lagp_mle_params* mle, bool have_sel, Plan* P);

@@ -176,7 +176,8 @@ struct lagp_server {
             std::copy(g.r->M.begin() + g.first, g.r->M.begin() + g.first + g.count, hm.begin() + g.at);
         }
         *P = Plan();
-        if (build_plan(design, &segs[0].r->prm, T, hn.data(), hm.data(), true, true, P)) return SIZE_MAX;
+        // one lane: the pieces in flight already overlap on the device
+        if (build_plan(design, &segs[0].r->prm, T, hn.data(), hm.data(), true, true, P, kChunk, 1)) return SIZE_MAX;
         return P->total + a256(T * sizeof(int32_t)) + io_bytes(T, P->nmax, design->dev.p);
     }
 
