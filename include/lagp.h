@@ -130,7 +130,12 @@ int lagp_knn(const lagp_design *design, const double *XX, int64_t T, int32_t M, 
  *   sel       optional device int32 T x sel_stride: chosen design indices in
  *             selection order (first n0 are the nearest neighbours);
  *   status    optional device int8[T]: LAGP_LOC_OK / LAGP_LOC_NOTPD.
- * Requires 1 <= n0 <= n <= ncand <= N for every location; sel_stride >= max n. */
+ * Requires 1 <= n0 <= n <= ncand <= N for every location; sel_stride >= max n.
+ * With n_per or ncand_per the call is not asynchronous: the planner groups
+ * the locations by size on the host, so it copies those arrays to the host
+ * and waits for the copy on `stream`.  Uneven batches that must not wait
+ * (graph capture, serving loops) use lagp_batch_*, whose sizes are host
+ * arrays given at creation. */
 int lagp_predict(const lagp_design *design, const double *XX, int64_t T, const lagp_params *params,
                  const int32_t *n_per, const int32_t *ncand_per, double *mean, double *s2,
                  int32_t *df, double *var, int32_t *sel, int64_t sel_stride, int8_t *status,
