@@ -474,7 +474,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
         // ---- gather candidates (coordinates and y into the coordinate block);
         //      K(x,c) and v_0(c) = 1 + g
         int ci[CPT];
-        double v[CPT], cov[CPT], d2[CPT];
+        // FP64 tile: yc = y_c - sum_l u_l W[l][c] tracks each candidate's
+        // whitened response the way cov tracks K(x,c) - sum_l w_x[l] W[l][c],
+        // so the chosen point's entries of w_x and u come from its owner.
+        double v[CPT], cov[CPT], d2[CPT], yc[CPT];
         TW Wr[RREG > 0 ? RREG : 1][CPT];
 #pragma unroll
         for (int l = 0; l < (RREG > 0 ? RREG : 1); ++l)
@@ -501,8 +504,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 }
                 d2[k] = sq;
                 cov[k] = exp(-div_by(sq, theta, rtheta));
+                yc[k] = MIX ? 0.0 : A.y[c];
             } else {
                 ci[k] = 0x7fffffff;
+                yc[k] = 0.0;
                 if (CL && ylds) Xc[(int64_t)p * Mpad + slot] = 0.0;
                 d2[k] = INFINITY;
                 cov[k] = 0.0;
@@ -612,6 +617,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                         for (int l = 0; l < (RREG > 0 ? RREG : 0); ++l)
                             if (l < i) ws[l] = Wr[l][k];
                         misc[0] = v[k];
+                        if (!MIX) {
+                            misc[2] = cov[k];
+                            misc[3] = yc[k];
+                        }
                         ctl[1] = ci[k];
                     }
                 }
@@ -619,14 +628,14 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             }
             for (int l = RREG + tid; l < i; l += DT)
                 ws[l] = (TW)((l < G0) ? Wl[(int64_t)(l - RREG) * Mpad + s] : Wg[(int64_t)(l - G0) * Mpad + s]);
-            // one response per step: from LDS when it holds them, else from the design
-            const double ys = (CL && ylds) ? Xc[(int64_t)p * Mpad + s] : A.y[cand[s]];
-            double ax, acc[CPT];
+            // K(x, s): the FP64 tile takes cov(s) from its owner after the
+            // barrier; the mixed modes' ranking tile evaluates it here.
+            double ax = 0.0, acc[CPT];
             if (P > 0) {
                 double xs[P > 0 ? P : 1];
 #pragma unroll
                 for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
-                ax = exp(-div_by(sqdist_lds<P>(xs, xl, 1, p), theta, rtheta));
+                if constexpr (MIX) ax = exp(-div_by(sqdist_lds<P>(xs, xl, 1, p), theta, rtheta));
                 // K(s, c) slot by slot: coordinates from LDS, or from the slab.
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
@@ -648,15 +657,17 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 for (int k = 0; k < CPT; ++k) sq[k] = 0.0;
                 for (int kk = 0; kk < p; ++kk) {
                     const double a = Xc[(int64_t)kk * Mpad + s];
-                    const double tx = a - xl[kk];
-                    sqx += tx * tx;
+                    if constexpr (MIX) {
+                        const double tx = a - xl[kk];
+                        sqx += tx * tx;
+                    }
 #pragma unroll
                     for (int k = 0; k < CPT; ++k) {
                         const double tc = a - Xc[(int64_t)kk * Mpad + tid + k * DT];
                         sq[k] += tc * tc;
                     }
                 }
-                ax = exp(-div_by(sqx, theta, rtheta));
+                if constexpr (MIX) ax = exp(-div_by(sqx, theta, rtheta));
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     acc[k] = exp(-div_by(sq[k], theta, rtheta));
@@ -686,7 +697,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             float dot[CPT], dotx = 0.0f;   // FP32 contraction (MIX)
 #pragma unroll
             for (int k = 0; k < CPT; ++k) dot[k] = 0.0f;
-            __syncthreads();   // B1: column of s and v(s) published
+            __syncthreads();   // B1: column of s, v(s) and its running sums published
 
             // The mixed mode's FP32 ranking stays self-consistent: its delta
             // is that of the tile's own v(s) (the exact one if that is not
@@ -695,7 +706,14 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (!MIX && !(vs > 0.0)) { notpd = 1; continue; }
             const double delta = (MIX && !(vs > 0.0)) ? dl[i] : sqrt(vs);
             const double rdelta = 1.0 / delta;
-            double ay = ys;
+            // FP64: the entries of w_x and u for s from its owner's running
+            // sums (the same products in the same ascending order as a dot
+            // product over the chosen column, so bitwise the same values).
+            double ay = 0.0;
+            if constexpr (!MIX) {
+                ax = misc[2];
+                ay = misc[3];
+            }
             // Row i of W for every live candidate: acc = K(s,c) - sum_l ws[l] W[l][c].
             // Register rows, four per block; rows >= i within a block are zero.
 #pragma unroll
@@ -703,8 +721,8 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 if (l0 < i) {
                     TW wv[4], xv[4];
                     ld4(ws + l0, wv);
-                    ld4(wx + l0, xv);
                     if constexpr (MIX) {
+                        ld4(wx + l0, xv);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -712,14 +730,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                             dotx = __builtin_fmaf(wv[r], xv[r], dotx);
                         }
                     } else {
-                        double uv[4];
-                        ld4(uu + l0, uv);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
 #pragma unroll
                             for (int k = 0; k < CPT; ++k) acc[k] -= wv[r] * Wr[l0 + r][k];
-                            ax -= wv[r] * xv[r];
-                            ay -= wv[r] * uv[r];
                         }
                     }
                 }
@@ -737,8 +751,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     } else {
 #pragma unroll
                         for (int k = 0; k < CPT; ++k) acc[k] -= wl * (TW)row[k * DT];
-                        ax -= wl * wx[l];
-                        ay -= wl * uu[l];
                     }
                 }
             }
@@ -754,8 +766,6 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     } else {
 #pragma unroll
                         for (int k = 0; k < CPT; ++k) acc[k] -= wl * b[k];
-                        ax -= wl * wx[l];
-                        ay -= wl * uu[l];
                     }
                 };
                 // Whole blocks of DEPTH rows with no exit inside a block, then
@@ -779,10 +789,11 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 for (int k = 0; k < CPT; ++k) acc[k] -= (double)dot[k];
             }
             const double rx = MIX ? ax * rdelta : div_by(ax, delta, rdelta);
+            const double ui = MIX ? 0.0 : div_by(ay, delta, rdelta);
             if (tid == 0) {
                 wx[i] = rx;
                 if (!MIX) {
-                    uu[i] = div_by(ay, delta, rdelta);
+                    uu[i] = ui;
                     misc[1] -= rx * rx;
                 }
                 if (A.sel) A.sel[t * A.sel_stride + i] = ctl[1];
@@ -793,6 +804,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 r[k] = MIX ? acc[k] * rdelta : div_by(acc[k], delta, rdelta);
                 v[k] -= r[k] * r[k];
                 cov[k] -= rx * r[k];
+                if (!MIX) yc[k] -= ui * r[k];
             }
             if (i < RREG) {
 #pragma unroll
