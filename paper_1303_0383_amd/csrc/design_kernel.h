@@ -185,7 +185,7 @@ __host__ __device__ constexpr int rreg_for(int dt, int cpt, bool cl, bool mix = 
             case 1: return 64;
             case 2: return 64;
             case 4: return 40;
-            default: return 16;
+            default: return (cl || trim) ? 16 : 20;
             }
         }
         switch (cpt) {
@@ -636,19 +636,33 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
 #pragma unroll
                 for (int k = 0; k < (P > 0 ? P : 1); ++k) xs[k] = Xc[(int64_t)k * Mpad + s];
                 if constexpr (MIX) ax = exp(-div_by(sqdist_lds<P>(xs, xl, 1, p), theta, rtheta));
-                // K(s, c) slot by slot: coordinates from LDS, or from the slab.
+                // K(s, c) in pairs of slots, coordinates from LDS or from the
+                // slab.  A pair's two chains interleave (with one wave per
+                // SIMD nothing else hides their latency); a runtime branch
+                // per pair (kact == CPT for full candidate sets) keeps the
+                // compiler from interleaving every slot's exponential, which
+                // would cost tile rows.
+                constexpr int KP = CPT >= 2 ? 2 : 1;
 #pragma unroll
-                for (int k = 0; k < CPT; ++k) {
-                    double sq;
-                    if constexpr (CL) sq = sqdist_lds<P>(xs, Xc + tid + k * DT, Mpad, p);
-                    else sq = sqdist_slab<(P > 0 ? P : 1)>(xs, slab, voff_c, k * DT * (int)sizeof(double),
-                                                           Mpad * (int)sizeof(double));
-                    // A runtime branch per slot (kact == CPT for full
-                    // candidate sets) keeps the compiler from interleaving
-                    // the slots' exponentials, which would cost tile rows.
-                    double e = 0.0;
-                    if (k < kact) e = exp(-div_by(sq, theta, rtheta));
-                    acc[k] = e;
+                for (int k0 = 0; k0 < CPT; k0 += KP) {
+                    double sq[KP], e[KP];
+#pragma unroll
+                    for (int q = 0; q < KP; ++q) {
+                        const int k = k0 + q;
+                        if constexpr (CL) sq[q] = sqdist_lds<P>(xs, Xc + tid + k * DT, Mpad, p);
+                        else sq[q] = sqdist_slab<(P > 0 ? P : 1)>(xs, slab, voff_c, k * DT * (int)sizeof(double),
+                                                                  Mpad * (int)sizeof(double));
+                        e[q] = 0.0;
+                    }
+                    if (k0 < kact) {
+#pragma unroll
+                        for (int q = 0; q < KP; ++q) {
+                            const double eq = exp(-div_by(sq[q], theta, rtheta));
+                            e[q] = k0 + q < kact ? eq : 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < KP; ++q) acc[k0 + q] = e[q];
                     asm volatile("" ::: "memory");
                 }
             } else {
