@@ -642,7 +642,7 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 // per pair (kact == CPT for full candidate sets) keeps the
                 // compiler from interleaving every slot's exponential, which
                 // would cost tile rows.
-                constexpr int KP = CPT >= 2 ? 2 : 1;
+                constexpr int KP = (CL && CPT >= 4) ? 4 : CPT >= 2 ? 2 : 1;
 #pragma unroll
                 for (int k0 = 0; k0 < CPT; k0 += KP) {
                     double sq[KP], e[KP];
