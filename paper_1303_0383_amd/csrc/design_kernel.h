@@ -103,17 +103,17 @@ __device__ __forceinline__ double div_by(double a, double b, double y)
 
 // ---- wave reductions with DPP (xor 1, xor 2 as quad permutes; rotations by
 // 4 and 8 inside each 16-lane row), then cross-row shuffles.
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ int dpp_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_d(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
-    const int hi = dpp_i<CTRL>((int)(b >> 32));
+    const int lo = dpp_i<CTRL, ROWS>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL, ROWS>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -271,6 +271,19 @@ __device__ __forceinline__ uint64_t wave_max_key(uint64_t k)
     const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)k, 63);
     const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 63);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// The wave's best triple in lane 63: row reductions, then row broadcasts
+// (lanes of rows outside a step's row mask compare with themselves).
+template <bool MAX>
+__device__ __forceinline__ void wave_pick63(double& v, int& i, int& s)
+{
+    pick<MAX>(v, i, s, dpp_d<0xB1>(v), dpp_i<0xB1>(i), dpp_i<0xB1>(s));     // xor 1
+    pick<MAX>(v, i, s, dpp_d<0x4E>(v), dpp_i<0x4E>(i), dpp_i<0x4E>(s));     // xor 2
+    pick<MAX>(v, i, s, dpp_d<0x124>(v), dpp_i<0x124>(i), dpp_i<0x124>(s));  // rotate 4 in row
+    pick<MAX>(v, i, s, dpp_d<0x128>(v), dpp_i<0x128>(i), dpp_i<0x128>(s));  // rotate 8 in row
+    pick<MAX>(v, i, s, dpp_d<0x142, 0xA>(v), dpp_i<0x142, 0xA>(i), dpp_i<0x142, 0xA>(s));  // lane 15 -> next row
+    pick<MAX>(v, i, s, dpp_d<0x143, 0xC>(v), dpp_i<0x143, 0xC>(i), dpp_i<0x143, 0xC>(s));  // lane 31 -> rows 2, 3
 }
 
 // ---- the per-workgroup global slab through a buffer descriptor: one
@@ -857,8 +870,8 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                             if (bs < 0 || better(a, ci[k], bv, bi)) { bv = a; bi = ci[k]; bs = tid + k * DT; }
                         }
                     }
-                    wave_pick<true>(bv, bi, bs);
-                    if (lane == 0) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
+                    wave_pick63<true>(bv, bi, bs);
+                    if (lane == 63) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
                 }
             } else {
                 // Mixed mode: a short list of the DWAVES best candidates by the
