@@ -858,18 +858,30 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             int bi = 0x7fffffff, bs = -1;
             if constexpr (!MIX) {
                 if (i + 1 >= n0) {
+                    // every slot's score, then the thread's best by a tree of
+                    // picks (the order is total, so any bracketing agrees)
+                    double av[CPT];
+                    int ai[CPT], as[CPT];
 #pragma unroll
                     for (int k = 0; k < CPT; ++k) {
-                        if (!((chosen >> k) & 1u)) {
-                            double a = -INFINITY;
-                            if (v[k] > 0.0) {
-                                double y = __builtin_amdgcn_rcp(v[k]);
-                                y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
-                                a = (cov[k] * cov[k]) * y;
-                            }
-                            if (bs < 0 || better(a, ci[k], bv, bi)) { bv = a; bi = ci[k]; bs = tid + k * DT; }
+                        double a = -INFINITY;
+                        if (v[k] > 0.0) {
+                            double y = __builtin_amdgcn_rcp(v[k]);
+                            y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
+                            a = (cov[k] * cov[k]) * y;
                         }
+                        const bool live = !((chosen >> k) & 1u);
+                        av[k] = live ? a : -INFINITY;
+                        ai[k] = live ? ci[k] : 0x7fffffff;
+                        as[k] = live ? tid + k * DT : -1;
                     }
+#pragma unroll
+                    for (int h = 1; h < CPT; h *= 2)
+#pragma unroll
+                        for (int k = 0; k + h < CPT; k += 2 * h) pick<true>(av[k], ai[k], as[k], av[k + h], ai[k + h], as[k + h]);
+                    bv = av[0];
+                    bi = ai[0];
+                    bs = as[0];
                     wave_pick63<true>(bv, bi, bs);
                     if (lane == 63) { redv[wave] = bv; redi[wave] = bi; reds[wave] = bs; }
                 }
