@@ -130,14 +130,15 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 __host__ __device__ __forceinline__ int packed_row(int l) { return l * (l + 1) / 2; }
 
 // Candidate ordering for the argmax: larger score first, then smaller index.
+// (Bitwise & and | on the comparisons: no short-circuit branches.)
 __device__ __forceinline__ bool better(double a, int ia, double b, int ib)
 {
-    return a > b || (a == b && ia < ib);
+    return (a > b) | ((a == b) & (ia < ib));
 }
 // Nearest-neighbour ordering: smaller squared distance first, then smaller index.
 __device__ __forceinline__ bool nearer(double a, int ia, double b, int ib)
 {
-    return a < b || (a == b && ia < ib);
+    return (a < b) | ((a == b) & (ia < ib));
 }
 
 // Four consecutive LDS doubles (16-byte aligned start) as two 16-byte reads.
@@ -224,8 +225,10 @@ __host__ __device__ constexpr int ring_depth(int cpt, bool mix)
 template <bool MAX>
 __device__ __forceinline__ void pick(double& v, int& i, int& s, double ov, int oi, int os)
 {
-    const bool take = os >= 0 && (s < 0 || (MAX ? better(ov, oi, v, i) : nearer(ov, oi, v, i)));
-    if (take) { v = ov; i = oi; s = os; }
+    const bool take = (os >= 0) & ((s < 0) | (MAX ? better(ov, oi, v, i) : nearer(ov, oi, v, i)));
+    v = take ? ov : v;
+    i = take ? oi : i;
+    s = take ? os : s;
 }
 
 template <bool MAX>
@@ -864,12 +867,10 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     int ai[CPT], as[CPT];
 #pragma unroll
                     for (int k = 0; k < CPT; ++k) {
-                        double a = -INFINITY;
-                        if (v[k] > 0.0) {
-                            double y = __builtin_amdgcn_rcp(v[k]);
-                            y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
-                            a = (cov[k] * cov[k]) * y;
-                        }
+                        // computed for every slot, kept where v > 0
+                        double y = __builtin_amdgcn_rcp(v[k]);
+                        y = __builtin_fma(__builtin_fma(-v[k], y, 1.0), y, y);
+                        const double a = (v[k] > 0.0) ? (cov[k] * cov[k]) * y : -INFINITY;
                         const bool live = !((chosen >> k) & 1u);
                         av[k] = live ? a : -INFINITY;
                         ai[k] = live ? ci[k] : 0x7fffffff;
