@@ -942,8 +942,15 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     // all waves' keys (rank = number of larger keys)
                     const int nl = DWAVES * NSHORT;
                     const uint64_t ke = lane < nl ? (uint64_t)__double_as_longlong(redv[2 * DWAVES + lane]) : 0ull;
+                    // every key broadcast from its lane (no LDS round trip per key)
+                    const uint32_t klo = (uint32_t)ke, khi = (uint32_t)(ke >> 32);
                     int rank = 0;
-                    for (int j = 0; j < nl; ++j) rank += (uint64_t)__double_as_longlong(redv[2 * DWAVES + j]) > ke;
+#pragma unroll
+                    for (int j = 0; j < nl; ++j) {
+                        const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, j) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)klo, j);
+                        rank += kj > ke;
+                    }
                     const uint64_t own = __ballot(lane < nl && ke != 0 && rank == wave);
                     if (own) {
                         const int el = __builtin_ctzll(own);
@@ -981,34 +988,45 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                     // (and lane + 64): row l subtracts L[l][m] W_m in ascending
                     // m, as the FP64 kernel does.  Rows at or above m and lanes
                     // past jr update too but are never read again, so no lane
-                    // predicate is needed.  delta_m, 1/delta_m, w_x[m] and L[l][m]
-                    // are read one iteration ahead; every read stays in LDS: a
-                    // lane past jr reads from row 0, and row l's reads end at
-                    // packed_row(l) + jr <= packed_row(jr) <= npk.
+                    // predicate is needed.  The factor entries L[l][m..m+3] and
+                    // delta, 1/delta, w_x for m..m+3 are read as a block before
+                    // the block's four dependent steps (one LDS latency per
+                    // block).  Every read stays in LDS: a lane past jr reads
+                    // from row 0, and row l's reads end at packed_row(l) + jr + 2
+                    // <= packed_row(jr) + 2, inside the arrays that follow the
+                    // factor.
                     auto solve = [&](auto two) {
                         constexpr bool TWO = decltype(two)::value;
+                        constexpr int U = 4;
                         const int r0 = lane < jr ? packed_row(lane) : 0;
                         const int r1 = (TWO && lane + 64 < jr) ? packed_row(lane + 64) : 0;
-                        double dm = dl[0], rm = rdl[0], xm = wx64[0];
-                        double f0 = Lf[r0], f1 = TWO ? Lf[r1] : 0.0;
-                        for (int m = 0; m < jr; ++m) {
-                            const double dn = dl[m + 1], rn = rdl[m + 1], xn = wx64[m + 1];
-                            const double g0 = f0, g1 = f1;
-                            f0 = Lf[r0 + m + 1];
-                            if constexpr (TWO) f1 = Lf[r1 + m + 1];
-                            const double am = (!TWO || m < 64) ? readlane_d(a0, m & 63) : readlane_d(a1, m & 63);
-                            const double W = div_by(am, dm, rm);
-                            vA -= W * W;
-                            cA -= xm * W;
-                            w0 = lane == m ? W : w0;
-                            a0 -= g0 * W;
-                            if constexpr (TWO) {
-                                w1 = lane + 64 == m ? W : w1;
-                                a1 -= g1 * W;
+                        for (int m0 = 0; m0 < jr; m0 += U) {
+                            double g0[U], g1[U], dm[U], rm[U], xm[U];
+#pragma unroll
+                            for (int q = 0; q < U; ++q) {
+                                g0[q] = Lf[r0 + m0 + q];
+                                g1[q] = TWO ? Lf[r1 + m0 + q] : 0.0;
+                                dm[q] = dl[m0 + q];
+                                rm[q] = rdl[m0 + q];
+                                xm[q] = wx64[m0 + q];
                             }
-                            dm = dn;
-                            rm = rn;
-                            xm = xn;
+#pragma unroll
+                            for (int q = 0; q < U; ++q) {
+                                const int m = m0 + q;
+                                if (m < jr) {
+                                    const double am =
+                                        (!TWO || m < 64) ? readlane_d(a0, m & 63) : readlane_d(a1, m & 63);
+                                    const double W = div_by(am, dm[q], rm[q]);
+                                    vA -= W * W;
+                                    cA -= xm[q] * W;
+                                    w0 = lane == m ? W : w0;
+                                    a0 -= g0[q] * W;
+                                    if constexpr (TWO) {
+                                        w1 = lane + 64 == m ? W : w1;
+                                        a1 -= g1[q] * W;
+                                    }
+                                }
+                            }
                         }
                     };
                     if (jr > 64) solve(std::integral_constant<bool, true>{});
