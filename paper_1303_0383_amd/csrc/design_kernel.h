@@ -1051,7 +1051,8 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
             if (MIX || i + 1 >= n0) {
                 bv = redv[0]; bi = redi[0]; bs = reds[0];
                 int bw = 0;
-                for (int w = 1; w < DWAVES; ++w) {
+                // (the mixed mode's entries past NSHORT are empty)
+                for (int w = 1; w < (MIX ? NSHORT : DWAVES); ++w) {
                     const int before = bs;
                     pick<true>(bv, bi, bs, redv[w], redi[w], reds[w]);
                     if (bs != before) bw = w;
