@@ -1010,22 +1010,24 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                                 rm[q] = rdl[m0 + q];
                                 xm[q] = wx64[m0 + q];
                             }
+                            // No branch inside a block (so the block's steps
+                            // interleave): a step past jr only updates rows
+                            // that are no longer read, and its v and cov terms
+                            // are dropped by selects.
 #pragma unroll
                             for (int q = 0; q < U; ++q) {
                                 const int m = m0 + q;
-                                if (m < jr) {
-                                    const double am =
-                                        (!TWO || m < 64) ? readlane_d(a0, m & 63) : readlane_d(a1, m & 63);
-                                    const double W = div_by(am, dm[q], rm[q]);
-                                    vA -= W * W;
-                                    cA -= xm[q] * W;
-                                    w0 = lane == m ? W : w0;
-                                    a0 -= g0[q] * W;
-                                    if constexpr (TWO) {
-                                        w1 = lane + 64 == m ? W : w1;
-                                        a1 -= g1[q] * W;
-                                    }
-                                }
+                                const double am =
+                                    (!TWO || m < 64) ? readlane_d(a0, m & 63) : readlane_d(a1, m & 63);
+                                const double W = div_by(am, dm[q], rm[q]);
+                                a0 -= g0[q] * W;
+                                if constexpr (TWO) a1 -= g1[q] * W;
+                                const bool ok = m < jr;
+                                const double vn = vA - W * W, cn = cA - xm[q] * W;
+                                vA = ok ? vn : vA;
+                                cA = ok ? cn : cA;
+                                w0 = lane == m ? W : w0;
+                                if constexpr (TWO) w1 = lane + 64 == m ? W : w1;
                             }
                         }
                     };
