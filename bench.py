@@ -514,7 +514,7 @@ def _saturate(S, prm, burst, steps, warmup):
     """Locations/s of the server with `burst` submitted at once and drained,
     over `steps` timed bursts after `warmup` untimed ones."""
     def step():
-        ts = [S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"]) for r in burst]
+        ts = [S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"], precision=prm.get("precision", 0)) for r in burst]
         for t in ts:
             S.wait(t)
 
@@ -541,7 +541,7 @@ def _open_loop(S, lagp, prm, reqs, rate):
         delay = start + r.arrival_s - mono()
         if delay > 0:
             time.sleep(delay)
-        tickets.append(S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"]))
+        tickets.append(S.submit(r.XX, prm["n0"], r.n, r.ncand, prm["d"], prm["g"], precision=prm.get("precision", 0)))
     lat, last = [], start
     for r, t in zip(reqs, tickets):
         o = S.wait(t)
@@ -585,7 +585,9 @@ def serve_bench(args, lagp, torch) -> int:
     Poisson arrivals at fractions of that rate give p50/p99 latency
     (completion minus scheduled arrival, open loop)."""
     import workloads
-    prm = workloads.C4_PARAMS
+    prec = {"fp64": lagp.LAGP_PREC_FP64, "fp32": lagp.LAGP_PREC_SCORE_FP32,
+            "bf16": lagp.LAGP_PREC_SCORE_BF16}[args.precision]
+    prm = dict(workloads.C4_PARAMS, precision=prec)
     X, y, _ = workloads.c4_design()
     D = lagp.Design(X, y)
     S = lagp.Server(D, args.budget_gib << 30)
@@ -607,11 +609,13 @@ def serve_bench(args, lagp, torch) -> int:
     dev = torch.device("cuda:0")
     XXd = torch.as_tensor(XX, device=dev)
     npd, mpd = torch.as_tensor(n_per, device=dev), torch.as_tensor(M_per, device=dev)
-    D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd)
+    D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd,
+              precision=prec)
     torch.cuda.synchronize()
     lagp.lagp_timing_enable(D.handle, True)
     lagp.lagp_phase_times(D.handle)
-    D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd)
+    D.predict(XXd, prm["n0"], int(n_per.max()), int(M_per.max()), prm["d"], prm["g"], n_per=npd, ncand_per=mpd,
+              precision=prec)
     torch.cuda.synchronize()
     phase, launches = lagp.lagp_phase_times(D.handle)
     knn_ms, des_ms = phase["knn"], phase["design"]
@@ -625,7 +629,9 @@ def serve_bench(args, lagp, torch) -> int:
     result = {
         "metric": METRIC, "value": round(sat, 1), "unit": "locations/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f64+f32-tile", "bf16": "f64+bf16-tile"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": "c4", "N": len(X), "p": 4, "n0": prm["n0"], "d": prm["d"], "g": prm["g"],
                    "burst_requests": args.burst, "burst_locations": burst_locs, "budget_gib": args.budget_gib},
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
