@@ -566,13 +566,12 @@ __global__ void __launch_bounds__(DT, 1) design_kernel(const DesignArgs A)
                 int bi = 0x7fffffff, bs = -1;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
-                    if (!((taken >> k) & 1u) && nearer(d2[k], ci[k], bd, bi)) {
-                        bd = d2[k]; bi = ci[k]; bs = tid + k * DT;
-                    }
+                    const bool live = !((taken >> k) & 1u);
+                    pick<false>(bd, bi, bs, live ? d2[k] : INFINITY, live ? ci[k] : 0x7fffffff, live ? tid + k * DT : -1);
                 }
-                wave_pick<false>(bd, bi, bs);
+                wave_pick63<false>(bd, bi, bs);
                 const int par = (r & 1) * DWAVES;
-                if (lane == 0) { redv[par + wave] = bd; redi[par + wave] = bi; reds[par + wave] = bs; }
+                if (lane == 63) { redv[par + wave] = bd; redi[par + wave] = bi; reds[par + wave] = bs; }
                 __syncthreads();
                 bd = redv[par]; bi = redi[par]; bs = reds[par];
                 for (int w = 1; w < DWAVES; ++w) pick<false>(bd, bi, bs, redv[par + w], redi[par + w], reds[par + w]);
