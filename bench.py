@@ -70,12 +70,16 @@ def mle_iterate_flops(n: int) -> float:
     return 8.0 / 3.0 * n ** 3
 
 
-def kernel_source_hash() -> str:
-    """Hash of the design kernel's sources: counter files record the hash they
-    were taken with, and a counter file taken with other sources is stale."""
+# Sources whose text decides each kernel's memory traffic.
+KERNEL_SOURCES = {"design_kernel": ("design_kernel.h", "design.hip"), "mspe_kernel": ("mspe.hip", "design_kernel.h")}
+
+
+def kernel_source_hash(kernel: str = "design_kernel") -> str:
+    """Hash of a kernel's sources: counter files record the hash they were
+    taken with, and a counter file taken with other sources is stale."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("design_kernel.h", "design.hip"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1303_0383_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,7 +96,7 @@ def read_traffic(kernel: str, workload: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha16") != kernel_source_hash():
+    if vals.get("kernel_source_sha16") != kernel_source_hash(kernel):
         return None
     return float(vals["bytes_per_launch"]) if "bytes_per_launch" in vals else None
 
