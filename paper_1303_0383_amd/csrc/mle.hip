@@ -178,12 +178,26 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                     if (tid == 0) u[m - 1] = u[m - 1] / dp;
                 }
                 if (tid == 0) piv[m] = sqrt(pm);
-                // trailing triangle rows i > m, columns m < k <= i; and u
+                // trailing triangle rows i > m, columns m < k <= i, folded into
+                // a rectangle: trailing row r (r + 1 entries) and trailing row
+                // tn - 1 - r (tn - r entries) share rectangle row r of tn + 1
+                // columns, so every thread runs the same number of items with
+                // no per-item row search; lanes 0..31 of a wave take rectangle
+                // rows, the wave's two halves and the other waves interleave
+                // its columns (thread 0 takes item (0, 0), the next pivot)
                 const int tn = n - m - 1;
-                for (int e = tid; e < tn * (tn + 1) / 2; e += MT) {
-                    const int ii = row_of(e), kk = e - half_prod(ii, ii + 1);
-                    const int i = m + 1 + ii, k = m + 1 + kk;
-                    Tm[tri(i, k)] -= (Tm[tri(i, m)] * Tm[tri(k, m)]) * rpm;
+                for (int r = tid & 31; r < ((tn + 1) >> 1); r += 32) {
+                    const int r2 = tn - 1 - r;   // >= r; equal for the middle row of an odd tn
+                    const int b1 = tri(m + 1 + r, 0), b2 = tri(m + 1 + r2, 0);
+                    const double l1 = Tm[b1 + m], l2 = Tm[b2 + m];
+                    const int cmax = r2 > r ? tn : r;   // the middle row has no partner
+                    for (int c = tid >> 5; c <= cmax; c += MT / 32) {
+                        const bool lower = c <= r;
+                        const int k = m + 1 + (lower ? c : c - r - 1);
+                        const double li = lower ? l1 : l2;
+                        const int o = (lower ? b1 : b2) + k;
+                        Tm[o] -= (li * Tm[tri(k, m)]) * rpm;
+                    }
                 }
                 const double um = u[m];
                 for (int i = m + 1 + tid; i < n; i += MT) u[i] -= (Tm[tri(i, m)] * um) * rpm;
@@ -237,6 +251,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             for (int b = tid; b < n; b += MT) {
                 double s = 0.0;
                 int o = tri(b, b);                 // (a, b), a = b, b + 1, ...: steps of a + 1
+#pragma unroll 4
                 for (int a = b; a < n; ++a) {
                     s += Tm[o] * u[a];
                     o += a + 1;
@@ -247,8 +262,10 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
             for (int a = tid; a < n; a += MT) {
                 double s = 0.0;
                 const double* ca = Cd + sl(a, 0);
+#pragma unroll 4
                 for (int b = 0; b < a; ++b) s += ca[b] * w[b];
                 int o = sl(a + 1, a);              // (b, a), b = a + 1, ...: steps of b
+#pragma unroll 4
                 for (int b = a + 1; b < n; ++b) {
                     s += Cd[o] * w[b];
                     o += b;
@@ -263,6 +280,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 acc[1] += w[a] * kw[a];
                 double z = 0.0;
                 const double* la = Tm + tri(a, 0);
+#pragma unroll 4
                 for (int b = 0; b <= a; ++b) z += la[b] * kw[b];
                 acc[2] += z * z;
             }
@@ -273,6 +291,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 const int a = row_of(e) + 1, b = e - half_prod(a, a - 1);
                 double ki = 0.0;
                 int oa = tri(a, a), ob = tri(a, b);   // rows k = a, a + 1, ...: steps of k + 1
+#pragma unroll 4
                 for (int k = a; k < n; ++k) {
                     ki += Tm[oa] * Tm[ob];
                     oa += k + 1;
@@ -303,8 +322,10 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                         const double* ca = Cd + sl(a, 0);
                         double s = 0.0;
                         const int b1 = a < j + 1 ? a : j + 1;
+#pragma unroll 4
                         for (int b = 0; b < b1; ++b) s += ca[b] * lj[b];
                         int o = sl(a + 1, a);
+#pragma unroll 4
                         for (int b = a + 1; b <= j; ++b) {
                             s += Cd[o] * lj[b];
                             o += b;
@@ -321,6 +342,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                         if (jj >= pw || i < j) continue;
                         double s = 0.0;
                         const double* li = Tm + tri(i, 0);
+#pragma unroll 4
                         for (int a = 0; a <= i; ++a) s += li[a] * H[a * PW + jj];
                         acc[6] += (i == j ? 1.0 : 2.0) * (s * s);
                     }
