@@ -531,6 +531,7 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
         for (int l = 1; l < c.lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(d->lane_stream[l - 1], d->lane_fork, 0);
         if (e != hipSuccess) return hip_fail("bucket lanes: fork", e);
     }
+    int rb = 0;
     for (const Bucket& b : c.buckets) {
         L.precision = P.prm.precision;
         L.T = b.count;
@@ -539,18 +540,22 @@ static int enqueue_designs(lagp_design* d, const Plan& P, const Chunk& c, lagp::
         L.order = order_dev ? order_dev + c.t0 + b.first : nullptr;
         hipStream_t ls = b.lane == 0 ? s : d->lane_stream[b.lane - 1];
         void* ws = (char*)des_ws + (size_t)b.lane * P.lane_b;
-        int r = lagp::design_run(d->dev, L, b.plan, ws, P.lane_b, ls, &err);
-        if (r) return fail(r == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        rb = lagp::design_run(d->dev, L, b.plan, ws, P.lane_b, ls, &err);
+        if (rb) break;
     }
     if (fork) {
+        // joined on the error path too: the caller's stream (or the capture)
+        // must not end while a lane still has work in flight
         hipError_t e = hipSuccess;
         for (int l = 1; l < c.lanes && e == hipSuccess; ++l) {
             e = hipEventRecord(d->lane_join[l - 1], d->lane_stream[l - 1]);
             if (e == hipSuccess) e = hipStreamWaitEvent(s, d->lane_join[l - 1], 0);
         }
-        if (e != hipSuccess) return hip_fail("bucket lanes: join", e);
         lk.unlock();
+        if (rb) return fail(rb == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
+        if (e != hipSuccess) return hip_fail("bucket lanes: join", e);
     }
+    if (rb) return fail(rb == -1 ? LAGP_E_INVAL : LAGP_E_HIP, err);
     if (P.mix) {
         // A location the mixed mode could not finish (its short list held no
         // candidate with a positive exact variance) is redone in FP64 from a
