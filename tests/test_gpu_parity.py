@@ -127,6 +127,37 @@ def test_knn_unrepresentative_sample(lagp, layout):
             assert np.array_equal(idx[t], ref), (layout, M, t)
 
 
+@pytest.mark.parametrize("layout", ["far", "tiny", "all_equal", "mixed_scales"])
+def test_knn_octave_clamps(lagp, layout):
+    """The first histogram bins squared distances by octave, clamped to
+    [2^-51, 2^11); keys outside that range all fall in an end bin and must be
+    resolved by the refinement passes (at most 18 in all): distances far above
+    2^11, far below 2^-51, a design of one repeated point (every key differs
+    only in its index), and a design spanning both clamps at once."""
+    r = np.random.default_rng(23)
+    N, p = 20000, 3
+    X = r.uniform(0.0, 1.0, (N, p))
+    XX = r.uniform(0.0, 1.0, (40, p))
+    if layout == "far":
+        X *= 1000.0                          # d^2 up to 3e6
+        XX *= 1000.0
+    elif layout == "tiny":
+        X *= 1e-12                           # d^2 near 1e-24
+        XX *= 1e-12
+    elif layout == "all_equal":
+        X[:] = X[0]
+    else:
+        X[: N // 2] *= 1e-12                 # half the design near the origin
+        X[N // 2:] *= 1000.0                 # the other half far out
+        XX = np.concatenate([XX[:20] * 1e-12, XX[20:] * 1000.0])
+    D = lagp.Design(X, np.zeros(N))
+    for M in (1, 50, 2000):
+        idx = _knn_gpu(D, XX, M)
+        for t in range(0, len(XX), 3):
+            ref, _ = oracle.knn(X, XX[t], M)
+            assert np.array_equal(idx[t], ref), (layout, M, t)
+
+
 # ------------------------------------------------------------- predict
 def test_predict_c0_full(c0):
     w, D = c0
