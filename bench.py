@@ -70,8 +70,10 @@ def mle_iterate_flops(n: int) -> float:
     return 8.0 / 3.0 * n ** 3
 
 
-# Sources whose text decides each kernel's memory traffic.
-KERNEL_SOURCES = {"design_kernel": ("design_kernel.h", "design.hip"), "mspe_kernel": ("mspe.hip", "design_kernel.h")}
+# Files whose text decides each kernel's memory traffic: its sources and, for
+# the design kernel, the tuned variant table (the variant sets the row split).
+KERNEL_SOURCES = {"design_kernel": ("design_kernel.h", "design.hip", os.path.join("..", "tune", "table.txt")),
+                  "mspe_kernel": ("mspe.hip", "design_kernel.h")}
 
 
 def kernel_source_hash(kernel: str = "design_kernel") -> str:
