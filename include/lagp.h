@@ -325,7 +325,7 @@ int lagp_design_set_variant_ex(lagp_design *design, int32_t threads, int32_t coo
  * each has its own workspace.
  * All server arrays are HOST memory; inputs are copied at submission.
  * Calls are thread-safe.  The server must be destroyed before its design.
- * slots: 0 (3) or 2..8; piece_locations: 0 (4096) or 1..131072; other
+ * slots: 0 (3) or 2..8; piece_locations: 0 (1024) or 1..131072; other
  * values give LAGP_E_INVAL.  lagp_server_create uses the defaults. */
 typedef struct lagp_server lagp_server;
 int lagp_server_create(const lagp_design *design, size_t hbm_budget_bytes, lagp_server **out);

@@ -39,7 +39,7 @@ namespace {
 
 constexpr int kSlotsDefault = 3;
 constexpr int kSlotsMax = 8;
-constexpr int32_t kPieceDefault = 4096;
+constexpr int32_t kPieceDefault = 1024;
 
 double now_s()
 {

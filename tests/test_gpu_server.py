@@ -138,7 +138,7 @@ def test_short_request_overtakes_long_work(c4, lagp):
           f"{1e3 * (o_s.submitted - o_b.submitted):.1f} ms later, served in {1e3 * (o_s.done - o_s.submitted):.1f} ms")
     assert o_b.submitted < o_s.submitted and o_s.done < o_b.done
     pieces, _, _, _ = S.stats()
-    assert pieces >= 16384 // 4096 + 1
+    assert pieces >= 16384 // 1024 + 1      # the default piece cap
     ref = gpu_predict(D, small, prm["n0"], 32, 1000, prm["d"], prm["g"])
     assert np.array_equal(o_s.mean, ref["mean"]) and np.array_equal(o_s.sel, ref["sel"][:, :32])
     ref = gpu_predict(D, big, prm["n0"], 100, 4000, prm["d"], prm["g"])
