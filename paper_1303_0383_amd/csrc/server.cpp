@@ -31,6 +31,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena_map.h"
 #include "lagp_runtime.h"
 
 using namespace lagp_rt;
@@ -76,48 +77,6 @@ size_t io_bytes(int64_t T, int32_t nmax, int p)
     return a256(T * p * sizeof(double)) + 2 * a256(T * sizeof(int32_t)) + 3 * a256(T * sizeof(double)) +
            a256(T * sizeof(int32_t)) + a256((size_t)T * nmax * sizeof(int32_t)) + a256(T);
 }
-
-// First-fit allocation of arena offsets; blocks are multiples of 256 bytes
-// and free neighbours merge on release.
-class ArenaMap {
-    std::map<size_t, size_t> free_;   // offset -> bytes
-public:
-    void reset(size_t bytes) { free_.clear(); free_[0] = bytes & ~(size_t)255; }
-    size_t largest() const
-    {
-        size_t m = 0;
-        for (const auto& f : free_) m = std::max(m, f.second);
-        return m;
-    }
-    bool alloc(size_t bytes, size_t* off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes, o = it->first;
-            free_.erase(it);
-            if (rest) free_[o + bytes] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 // Locations [first, first + count) of a request, at offset `at` of a piece.
 struct Segment {
