@@ -219,6 +219,19 @@ knn_hist_kernel(const double* __restrict__ Xa, int64_t N, int p, const double* _
             bump(exp_bin((uint64_t)__double_as_longlong(d2)));
         };
         scan_rows<P>(Xa, i0, i1, x, p, bin);
+    } else if (__all(aligned)) {
+        // Every window of the wave (and so every bin) is bounded by whole
+        // distance values: 64-bit arithmetic on the distance bits decides
+        // each key, with no per-row choice between the two forms below.
+        const int sh = shift - 31;
+        auto bin = [&](double d2, int64_t) {
+            uint64_t bits = (uint64_t)__double_as_longlong(d2);
+            const bool under = bits < lo_d;
+            nbelow += (under && cbelow) ? 1u : 0u;
+            if (under || bits > hi_d) return;
+            bump((int)((bits - lo_d) >> sh));
+        };
+        scan_rows<P>(Xa, i0, i1, x, p, bin);
     } else {
         auto bin = [&](double d2, int64_t gi) {
             uint64_t bits = (uint64_t)__double_as_longlong(d2);
@@ -436,14 +449,20 @@ knn_collect_kernel(const double* __restrict__ Xa, int64_t N, int p, const double
         const uint32_t b0 = atomicAdd(counts + 2 * t + 1, (uint32_t)n);
         for (int j = 0; j < n; ++j) put(b0 + j, kbits[j * KNN_THREADS + tid], kidx[j * KNN_THREADS + tid]);
     };
+    // Windows bounded by whole distance values (the low 31 key bits zero at
+    // both ends) are decided by the distance bits alone: key < lo exactly
+    // when bits < lo_d, and key < hi exactly when bits <= hi_d.
+    const u128 low31 = ((u128)1 << 31) - 1;
+    const bool aligned = ((lo & low31) == 0) && ((hi & low31) == 0);
+    const bool fast = __all(aligned);
     auto take = [&](double d2, int64_t gi) {
         uint64_t bits = (uint64_t)__double_as_longlong(d2);
         if (bits > hi_d) return;
         // the full key only at or above the window's first distance value
         const bool under = bits < lo_d;
         u128 key = 0;
-        if (!under) key = ((u128)bits << 31) | (uint64_t)gi;
-        if (under || key < lo) {
+        if (!under && !fast) key = ((u128)bits << 31) | (uint64_t)gi;
+        if (under || (!fast && key < lo)) {
             if (!split) {
                 out[nbelow++] = (int32_t)gi;
             } else {
@@ -455,7 +474,7 @@ knn_collect_kernel(const double* __restrict__ Xa, int64_t N, int p, const double
                     ns = 0;
                 }
             }
-        } else if (key < hi) {
+        } else if (fast || key < hi) {
             if (!split) {
                 put(nbkt++, bits, (uint32_t)gi);
             } else {
