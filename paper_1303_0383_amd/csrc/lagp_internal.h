@@ -192,6 +192,7 @@ struct MspeArgs {
     double* scratch = nullptr;      // blocks x scratch_stride doubles
     int64_t scratch_stride = 0;
     unsigned int* counter = nullptr;
+    int lds_rows = 0;               // leading tile rows kept in LDS (set by mspe_run)
 };
 size_t mspe_lds_bytes(int nmax, int p);
 size_t mspe_slab_bytes(int nmax, int Mmax, int p);

@@ -35,6 +35,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "design_kernel.h"
 
 namespace lagp {
@@ -51,6 +53,16 @@ enum {
 __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 // symmetric matrix stored as its packed lower triangle
 __device__ __forceinline__ int sym(int i, int k) { return i >= k ? tri(i, k) : tri(k, i); }
+
+// Bytes of the kernel's LDS arrays (the factor, the bordered matrices and the
+// vectors below); LDS tile rows start at the next 8-byte boundary.
+__host__ __device__ inline size_t lds_base_bytes(int nmax, int p)
+{
+    const size_t nm = (size_t)nmax;
+    const size_t d = 3 * nm * (nm + 1) / 2 + nm * p + 14 * nm + 2 * (size_t)p + NSCAL + MAXWAVES;
+    const size_t i = 2 * MAXWAVES + nm + 4;
+    return d * sizeof(double) + i * sizeof(int);
+}
 
 // Sum over the 64 lanes of wave 0 (result in every lane of that wave).
 __device__ __forceinline__ double wave_sum(double v)
@@ -109,6 +121,11 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
     double* Xc = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;   // [p][Mpad] candidate coordinates
     double* Wt = Xc + (int64_t)p * Mpad;                                // [nm-1][Mpad] W rows
     double* Wdt = Wt + (int64_t)(nm - 1) * Mpad;                        // [nm-1][Mpad] Wd rows
+    // The first RL rows of both tiles live in the LDS left over by the
+    // arrays above (their slab rows stay unused); the rest stream from the slab.
+    const int RL = A.lds_rows;
+    double* Wl = smem + (lds_base_bytes(nm, p) + 7) / 8;   // [RL][Mpad] W rows
+    double* Wdl = Wl + (size_t)RL * Mpad;                  // [RL][Mpad] Wd rows
 
     for (;;) {
         if (tid == 0) ctl[0] = (int)atomicAdd(A.counter, 1u);
@@ -195,8 +212,9 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
                 chosen |= 1u << kk;
             }
             for (int l = tid; l < i; l += MT) {
-                ws[l] = Wt[(int64_t)l * Mpad + s];
-                wds[l] = Wdt[(int64_t)l * Mpad + s];
+                const bool on = l < RL;
+                ws[l] = on ? Wl[(size_t)l * Mpad + s] : Wt[(int64_t)l * Mpad + s];
+                wds[l] = on ? Wdl[(size_t)l * Mpad + s] : Wdt[(int64_t)l * Mpad + s];
             }
             for (int kk = tid; kk < p; kk += MT) {
                 const double c = Xc[(int64_t)kk * Mpad + s];
@@ -306,16 +324,31 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
             double d1[CPT], dz[CPT], dh[CPT], d4[CPT];
 #pragma unroll
             for (int k = 0; k < CPT; ++k) d1[k] = dz[k] = dh[k] = d4[k] = 0.0;
-            // rows stream with the next row's loads in flight during this row's arithmetic
-            double nw[CPT], nwd[CPT];
-            if (i > 0) {
+            // rows in LDS first, then the slab's rows stream with the next
+            // row's loads in flight during this row's arithmetic (ascending
+            // rows throughout)
+            const int il = i < RL ? i : RL;
+            for (int l = 0; l < il; ++l) {
+                const double wl = ws[l], zl = z[l], hl = h[l];
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
-                    nw[k] = Wt[tid + k * MT];
-                    nwd[k] = Wdt[tid + k * MT];
+                    const double cw = Wl[(size_t)l * Mpad + tid + k * MT];
+                    const double cwd = Wdl[(size_t)l * Mpad + tid + k * MT];
+                    d1[k] += wl * cw;
+                    dz[k] += zl * cw;
+                    dh[k] += hl * cw;
+                    d4[k] += wl * cwd;
                 }
             }
-            for (int l = 0; l < i; ++l) {
+            double nw[CPT], nwd[CPT];
+            if (i > il) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    nw[k] = Wt[(int64_t)il * Mpad + tid + k * MT];
+                    nwd[k] = Wdt[(int64_t)il * Mpad + tid + k * MT];
+                }
+            }
+            for (int l = il; l < i; ++l) {
                 double cw[CPT], cwd[CPT];
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) { cw[k] = nw[k]; cwd[k] = nwd[k]; }
@@ -348,9 +381,11 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
                 const double ksc = exp(-(d2 / theta));
                 const double r = (ksc - d1[k]) / delta;
                 const double wdn = (ksc * d2 / th2 - d4[k]) / delta;
+                double* wrow = i < RL ? Wl + (size_t)i * Mpad : Wt + (int64_t)i * Mpad;
+                double* wdrow = i < RL ? Wdl + (size_t)i * Mpad : Wdt + (int64_t)i * Mpad;
                 if (!((chosen >> k) & 1u)) {
-                    Wt[(int64_t)i * Mpad + slot] = r;
-                    Wdt[(int64_t)i * Mpad + slot] = wdn;
+                    wrow[slot] = r;
+                    wdrow[slot] = wdn;
                     v[k] -= r * r;
                     cov[k] -= wxi * r;
                     av[k] += wdn * ui;
@@ -358,8 +393,8 @@ __global__ void __launch_bounds__(MT, 1) mspe_kernel(const MspeArgs A)
                     Qv[k] += 2.0 * r * dh[k] + r * r * hi;
                     zc[k] = dz[k] + zi * r;
                 } else {
-                    Wt[(int64_t)i * Mpad + slot] = 0.0;
-                    Wdt[(int64_t)i * Mpad + slot] = 0.0;
+                    wrow[slot] = 0.0;
+                    wdrow[slot] = 0.0;
                 }
             }
             // ---- argmin of J over live candidates (from step n0 on)
@@ -440,13 +475,7 @@ int cpt_for(int M)
 
 }  // namespace
 
-size_t mspe_lds_bytes(int nmax, int p)
-{
-    const size_t nm = (size_t)nmax;
-    const size_t d = 3 * nm * (nm + 1) / 2 + nm * p + 14 * nm + 2 * (size_t)p + NSCAL + MAXWAVES;
-    const size_t i = 2 * MAXWAVES + nm + 4;
-    return d * sizeof(double) + i * sizeof(int);
-}
+size_t mspe_lds_bytes(int nmax, int p) { return lds_base_bytes(nmax, p); }
 
 size_t mspe_slab_bytes(int nmax, int Mmax, int p)
 {
@@ -466,11 +495,17 @@ int mspe_prepare(int32_t nmax, int32_t Mmax, int p, size_t max_lds, std::string*
     return 0;
 }
 
-int mspe_run(const MspeArgs& a, int blocks, size_t max_lds, hipStream_t stream, std::string* err)
+int mspe_run(const MspeArgs& args, int blocks, size_t max_lds, hipStream_t stream, std::string* err)
 {
-    if (a.T == 0) return 0;
-    const size_t lds = mspe_lds_bytes(a.nmax, a.p);
-    if (lds > max_lds) { *err = "local design too large for the MSPE kernel"; return -1; }
+    if (args.T == 0) return 0;
+    const size_t base = (lds_base_bytes(args.nmax, args.p) + 7) & ~(size_t)7;
+    if (base > max_lds) { *err = "local design too large for the MSPE kernel"; return -1; }
+    // as many leading tile rows (W and Wd) as the LDS left over holds
+    MspeArgs a = args;
+    const size_t pair = 2 * (size_t)cpt_for(a.M) * threads_for(a.M) * sizeof(double);
+    const size_t fit = (max_lds - base) / pair;
+    a.lds_rows = (int)std::min<size_t>(fit, (size_t)(a.nmax > 1 ? a.nmax - 1 : 0));
+    const size_t lds = base + (size_t)a.lds_rows * pair;
     fill_u32(a.counter, 1, 0u, stream);
     const int c = cpt_for(a.M);
     int rc;
