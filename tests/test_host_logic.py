@@ -102,3 +102,13 @@ def test_serving_request_stream_is_seeded():
     assert all(1 <= len(r.XX) <= 512 and r.n in (32, 50, 64, 100) and 1000 <= r.ncand <= 4000 for r in a)
     t = [r.arrival_s for r in a]
     assert all(t1 > t0 for t0, t1 in zip(t, t[1:]))
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; a request for more exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2 and "exactly one GPU" in out.stderr and out.stdout == ""
