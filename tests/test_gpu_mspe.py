@@ -114,7 +114,9 @@ def test_mspe_c2_matches_oracle(lagp):
 
 
 def test_mspe_slot_counts(lagp):
-    """Candidate-set sizes that use 1, 2 and 4 slots per thread."""
+    """Candidate-set sizes that use 1, 2 and 4 slots per thread; at n = 20
+    they also keep all, all but one, and about half of the tile rows in the
+    LDS the kernel leaves free (the rest stream from the slab)."""
     w = workloads.c0()
     D = lagp.Design(w.X, w.y)
     XX = w.XX[:12]
