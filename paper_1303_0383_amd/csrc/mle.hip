@@ -49,7 +49,19 @@ namespace lagp {
 
 namespace {
 
-constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product
+constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product (designs above 64 points)
+constexpr int MF = 64;  // designs of up to MF points take the panel products on the matrix cores
+
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+// Doubles of the panel buffer: two PW-wide panels, or for designs of up to MF
+// points one 16-column panel over the design padded to a multiple of 16.
+__host__ __device__ inline size_t panel_doubles(int nm)
+{
+    const size_t a = 2 * (size_t)nm * PW;
+    const size_t b = nm <= MF ? (size_t)((nm + 15) & ~15) * 16 : 0;
+    return a > b ? a : b;
+}
 constexpr int NRED = 7; // sums reduced per iterate
 
 // Packed indices.  Every index here is far below 2^24, so the products use
@@ -102,7 +114,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NRED], double* red, int ti
 }
 
 template <int MT>
-__global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
+__global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) mle_kernel(const MleArgs A)
 {
     extern __shared__ double sm[];
     if ((int64_t)blockIdx.x >= A.T) return;
@@ -116,8 +128,8 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
     double* xs = sm;                              // [nmax][p] design coordinates
     double* Tm = xs + (size_t)nm * p;             // packed lower: K -> L -> L^{-1}
     double* Cd = Tm + (size_t)nm * (nm + 1) / 2;  // packed strictly lower: dK
-    double* Hb = Cd + (size_t)nm * (nm - 1) / 2;  // [2][nmax][PW] panels of dK L^{-T}
-    double* yv = Hb + 2 * (size_t)nm * PW;        // Y
+    double* Hb = Cd + (size_t)nm * (nm - 1) / 2;  // panels of dK L^{-T} ([2][nmax][PW], or [16 ceil(n/16)][16])
+    double* yv = Hb + panel_doubles(nm);          // Y
     double* u = yv + nm;                          // L^{-1} Y
     double* w = u + nm;                           // K^{-1} Y
     double* kw = w + nm;                          // dK K^{-1} Y
@@ -304,9 +316,51 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                 acc[4] += 2.0 * ki * kd;
                 acc[5] += 2.0 * ki * kdd;
             }
-            // ---- tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2, PW columns at a time:
-            //      phase ph forms panel ph of H = dK L^{-T} and, from the other
-            //      buffer, the entries M_ij (i >= j) of panel ph - 1
+            // ---- tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2
+            if (nm <= MF) {
+                // On the matrix cores (FP64, 16 x 16 x 4 per instruction), over
+                // the design padded with zero rows and columns to np16 = 16
+                // ceil(n/16): a 16-column panel of H = dK L^{-T} (one 16 x 16
+                // tile per wave), staged in LDS, then the same columns of
+                // M = L^{-1} H, whose squared entries (all of them: M is
+                // symmetric) sum to the trace.  Operand layout of the
+                // instruction: A[i][k] and B[k][j] come from lane i + 16 k and
+                // j + 16 k, and lane l's result r is D[4 r + l / 16][l % 16].
+                const int np16 = (n + 15) & ~15, nt = np16 / 16;
+                const int lane = tid & 63, wave = tid >> 6;
+                const int li = lane & 15, lk = lane >> 4;
+                for (int q = 0; q < nt; ++q) {
+                    const int j = 16 * q + li;   // this lane's column of H and M
+                    for (int tw = wave; tw < nt; tw += MT / 64) {
+                        const int a = 16 * tw + li;   // row of dK
+                        mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+                        for (int k0 = 0; k0 < np16; k0 += 4) {
+                            const int b = k0 + lk;
+                            double av = 0.0, bv = 0.0;
+                            if (a < n && b < n && a != b) av = a > b ? Cd[sl(a, b)] : Cd[sl(b, a)];
+                            if (j < n && b <= j) bv = Tm[tri(j, b)];   // L^{-T}[b][j] = Li_jb
+                            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Hb[(16 * tw + 4 * r + lk) * 16 + li] = c[r];
+                    }
+                    __syncthreads();
+                    for (int tw = wave; tw < nt; tw += MT / 64) {
+                        const int i = 16 * tw + li;   // row of L^{-1} and M
+                        mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+                        for (int k0 = 0; k0 < np16; k0 += 4) {
+                            const int a = k0 + lk;
+                            const double av = (i < n && a <= i) ? Tm[tri(i, a)] : 0.0;
+                            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Hb[a * 16 + li], c, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[6] += c[r] * c[r];
+                    }
+                    __syncthreads();
+                }
+            } else {
+            // PW columns at a time: phase ph forms panel ph of H = dK L^{-T}
+            // and, from the other buffer, the entries M_ij (i >= j) of panel ph - 1
             const int np = (n + PW - 1) / PW;
             for (int ph = 0; ph <= np; ++ph) {
                 if (ph < np) {
@@ -348,6 +402,7 @@ __global__ void __launch_bounds__(MT) mle_kernel(const MleArgs A)
                     }
                 }
                 __syncthreads();
+            }
             }
             block_sum<MT>(acc, red, tid);
             if (tid == 0) {
@@ -397,7 +452,7 @@ int threads_for(int nmax)
 size_t mle_lds_bytes(int nmax, int p, int threads)
 {
     const size_t nm = (size_t)nmax;
-    return (nm * p + nm * (nm + 1) / 2 + nm * (nm - 1) / 2 + 2 * nm * PW + 7 * nm + (size_t)NRED * (threads / 64)) *
+    return (nm * p + nm * (nm + 1) / 2 + nm * (nm - 1) / 2 + panel_doubles(nmax) + 7 * nm + (size_t)NRED * (threads / 64)) *
            sizeof(double);
 }
 
