@@ -27,9 +27,11 @@
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
 //     K^{-1} = L^{-T} L^{-1} computed as they are used, and
-//     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of PW columns of
-//     H = dK L^{-T} at a time (one panel formed while the previous one is
-//     used);
+//     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of columns of
+//     H = dK L^{-T} at a time: for designs of up to 64 points 16 columns on
+//     the FP64 matrix cores, then the same columns of L^{-1} H; larger
+//     designs PW columns on the vector unit (one panel formed while the
+//     previous one is used);
 //   * takes the safeguarded Newton step on l'(theta) = 0.
 // The step rule: where l'' < 0 the step is -l'/l''; elsewhere it is theta in
 // the direction of l'; a step leaving (tmin, tmax) goes half way to the
