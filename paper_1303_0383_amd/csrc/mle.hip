@@ -28,7 +28,7 @@
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
 //     K^{-1} = L^{-T} L^{-1} computed as they are used, and
 //     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of columns of
-//     H = dK L^{-T} at a time: for designs of up to 64 points 16 columns on
+//     H = dK L^{-T} at a time: for designs of up to 128 points 16 columns on
 //     the FP64 matrix cores, then the same columns of L^{-1} H; larger
 //     designs PW columns on the vector unit (one panel formed while the
 //     previous one is used);
@@ -51,8 +51,8 @@ namespace lagp {
 
 namespace {
 
-constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product (designs above 64 points)
-constexpr int MF = 64;  // designs of up to MF points take the panel products on the matrix cores
+constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product (designs above MF points)
+constexpr int MF = 128; // designs of up to MF points take the panel products on the matrix cores
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
