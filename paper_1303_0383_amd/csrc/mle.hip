@@ -18,8 +18,11 @@
 //   * builds K (packed lower triangle) and dK (packed strictly-lower
 //     triangle) from the design coordinates held in LDS;
 //   * factorises K right-looking in place, carrying u = L^{-1} Y, and keeps
-//     the pivots L_kk -- one barrier per column, each column scaled during
-//     the next column's phase;
+//     the pivots L_kk -- for designs of up to 128 points by 16-column panels
+//     (one wave factors a panel with its rows in registers, the trailing
+//     blocks take the panel's rank-16 update on the FP64 matrix cores),
+//     for larger ones one barrier per column, each column scaled during the
+//     next column's phase;
 //   * overwrites L with L^{-1} in place by Gauss-Jordan elimination, one
 //     barrier per column (each row scaled during the next phase, the next
 //     column of L copied aside first);
@@ -55,6 +58,15 @@ constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product (designs
 constexpr int MF = 128; // designs of up to MF points take the panel products on the matrix cores
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+// The value v holds in lane l of the wave (l constant across the wave).
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 
 // Doubles of the panel buffer: two PW-wide panels, or for designs of up to MF
 // points one 16-column panel over the design padded to a multiple of 16.
@@ -182,6 +194,121 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
             // also updates the next pivot (trailing item 0), and passed on in
             // red[0..1] (free until the sums at the end of the iterate).
             int fail = 0;
+            if (nm <= MF) {
+                // Blocked by 16 columns: one wave factors a 16-column panel
+                // (lanes over rows, no barrier: LDS operations of a wave
+                // complete in issue order), scaling each column by its root
+                // and carrying u = L^{-1} Y; then the trailing blocks take the
+                // panel's rank-16 update as 16 x 16 x 16 products on the FP64
+                // matrix cores (one 16 x 16 block per wave at a time).  The
+                // diagonal keeps the unrooted pivots, the roots go to piv.
+                const int lane = tid & 63, wave = tid >> 6;
+                const int li = lane & 15, lk = lane >> 4;
+                const int nb = (n + 15) >> 4;
+                for (int kb = 0; kb < nb && !fail; ++kb) {
+                    const int c0 = 16 * kb, c1 = (c0 + 16 < n) ? c0 + 16 : n;
+                    if (wave == 0) {
+                        // lane l holds the panel part of row c0 + l in registers for
+                        // all 16 steps; row m of the panel is lane m - c0's row, read
+                        // across lanes.  Rows c0 + 64 + l (designs above 64 points)
+                        // follow in a second pass that reads the finished panel
+                        // columns, roots and u back from LDS.
+                        const int i0 = c0 + lane;
+                        const bool h0 = i0 < n;
+                        const int b0 = h0 ? tri(i0, 0) : 0;
+                        double r0[16];
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int k = c0 + q;
+                            r0[q] = (h0 && k < c1 && k <= i0) ? Tm[b0 + k] : 0.0;
+                        }
+                        double u0 = h0 ? u[i0] : 0.0;
+                        int f = 0;
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            if (c0 + q < c1 && !f) {
+                                const double pm = lane_value(r0[q], q);
+                                if (!(pm > 0.0)) {
+                                    f = 1;   // uniform: every lane read the same pivot
+                                } else {
+                                    const double dp = sqrt(pm);
+                                    const double um = lane_value(u0, q) / dp;
+                                    if (lane == q) u0 = um;
+                                    if (lane == 0) piv[c0 + q] = dp;
+                                    if (lane > q) r0[q] = r0[q] / dp;   // rows below the pivot
+#pragma unroll
+                                    for (int qq = q + 1; qq < 16; ++qq) {
+                                        const double lkm = lane_value(r0[q], qq);   // L_km, row k = c0 + qq
+                                        if (lane >= qq) r0[qq] -= r0[q] * lkm;
+                                    }
+                                    if (lane > q) u0 -= r0[q] * um;
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int k = c0 + q;
+                            if (h0 && k < c1 && k <= i0) Tm[b0 + k] = r0[q];
+                        }
+                        if (h0) u[i0] = u0;
+                        if (!f && c0 + 64 < n) {
+                            __builtin_amdgcn_wave_barrier();
+                            const int i1 = c0 + 64 + lane;
+                            const bool h1 = i1 < n;
+                            const int b1 = h1 ? tri(i1, 0) : 0;
+                            double r1[16];
+#pragma unroll
+                            for (int q = 0; q < 16; ++q) r1[q] = (h1 && c0 + q < c1) ? Tm[b1 + c0 + q] : 0.0;
+                            double u1 = h1 ? u[i1] : 0.0;
+#pragma unroll
+                            for (int q = 0; q < 16; ++q) {
+                                if (c0 + q < c1) {
+                                    const int m = c0 + q;
+                                    r1[q] = r1[q] / piv[m];
+#pragma unroll
+                                    for (int qq = q + 1; qq < 16; ++qq)
+                                        if (c0 + qq < c1) r1[qq] -= r1[q] * Tm[tri(c0 + qq, m)];
+                                    u1 -= r1[q] * u[m];
+                                }
+                            }
+#pragma unroll
+                            for (int q = 0; q < 16; ++q)
+                                if (h1 && c0 + q < c1) Tm[b1 + c0 + q] = r1[q];
+                            if (h1) u[i1] = u1;
+                        }
+                        if (lane == 0) red[0] = f ? 1.0 : 0.0;
+                    }
+                    __syncthreads();
+                    if (red[0] != 0.0) { fail = 1; break; }   // uniform
+                    // trailing blocks (ib, jb), kb < jb <= ib < nb: A_ib,jb -= L_ib,kb L_jb,kb^T
+                    const int ntb = nb - kb - 1;
+                    for (int tt = wave; tt < ntb * (ntb + 1) / 2; tt += MT / 64) {
+                        int ib = kb + 1, rem = tt;
+                        while (rem >= ib - kb) { rem -= ib - kb; ++ib; }
+                        const int jb = kb + 1 + rem;
+                        mf_d4 c;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = 16 * ib + 4 * r + lk, j = 16 * jb + li;
+                            c[r] = (i < n && j <= i) ? Tm[tri(i, j)] : 0.0;
+                        }
+                        const int ia = 16 * ib + li, ja = 16 * jb + li;
+#pragma unroll
+                        for (int k0 = 0; k0 < 16; k0 += 4) {
+                            const int kc = c0 + k0 + lk;
+                            const double av = (ia < n && kc < c1) ? -Tm[tri(ia, kc)] : 0.0;
+                            const double bv = (ja < n && kc < c1) ? Tm[tri(ja, kc)] : 0.0;
+                            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = 16 * ib + 4 * r + lk, j = 16 * jb + li;
+                            if (i < n && j <= i) Tm[tri(i, j)] = c[r];
+                        }
+                    }
+                    __syncthreads();
+                }
+            } else {
             for (int m = 0; m < n; ++m) {
                 const double pm = Tm[tri(m, m)];
                 if (!(pm > 0.0)) { fail = 1; break; }   // uniform: every thread read the same pivot
@@ -218,11 +345,12 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                 if (tid == 0 && m + 1 < n) red[(m + 1) & 1] = 1.0 / Tm[tri(m + 1, m + 1)];
                 __syncthreads();
             }
+            if (!fail && tid == 0) u[n - 1] = u[n - 1] / piv[n - 1];   // column n-1 has no entries below its pivot
+            }
             if (fail) {
                 if (tid == 0) bad = 1;
                 break;
             }
-            if (tid == 0) u[n - 1] = u[n - 1] / piv[n - 1];   // column n-1 has no entries below its pivot
             // ---- L^{-1} in place, one barrier per column: row k of X = L^{-1} is
             //      used unscaled (times 1/L_kk on the fly) and scaled during the
             //      next phase; column k+1 of L is copied aside in phase k (two
