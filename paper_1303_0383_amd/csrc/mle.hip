@@ -23,9 +23,13 @@
 //     blocks take the panel's rank-16 update on the FP64 matrix cores),
 //     for larger ones one barrier per column, each column scaled during the
 //     next column's phase;
-//   * overwrites L with L^{-1} in place by Gauss-Jordan elimination, one
-//     barrier per column (each row scaled during the next phase, the next
-//     column of L copied aside first);
+//   * overwrites L with L^{-1} in place -- for designs of up to 128 points
+//     by 16x16 blocks (each diagonal block inverted by one wave in
+//     registers, then block row i of the inverse as -X_ii times the sum over
+//     k < i of L_ik X_kj, both products on the FP64 matrix cores), for
+//     larger ones by Gauss-Jordan elimination, one barrier per column (each
+//     row scaled during the next phase, the next column of L copied aside
+//     first);
 //   * forms w = K^{-1} Y = L^{-T} u and k = dK w, and from them
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
@@ -351,6 +355,86 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                 if (tid == 0) bad = 1;
                 break;
             }
+            if (nm <= MF) {
+                // ---- L^{-1} in place by 16 x 16 blocks: each diagonal block
+                //      X_ii = L_ii^{-1} by one wave (lane = row, the row kept in
+                //      registers, earlier rows read across lanes), then block row
+                //      by block row X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj on the
+                //      FP64 matrix cores (the sums staged in LDS first, since they
+                //      read L blocks of the row that the products overwrite).
+                const int lane = tid & 63, wave = tid >> 6;
+                const int li = lane & 15, lk = lane >> 4;
+                const int nb = (n + 15) >> 4;
+                for (int kb = wave; kb < nb; kb += MT / 64) {
+                    const int c0 = 16 * kb, i = c0 + li;
+                    const bool hv = lane < 16 && i < n;
+                    double xr[16];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) xr[c] = 0.0;   // sums of L_im X_mc over m < i
+#pragma unroll
+                    for (int m = 0; m < 16; ++m) {
+                        if (c0 + m < n) {
+                            // row m finishes: X_mc = -sum / L_mm (c < m), X_mm = 1 / L_mm
+                            if (lane == m) {
+                                const double dm = piv[c0 + m];
+#pragma unroll
+                                for (int c = 0; c < 16; ++c)
+                                    if (c < m) xr[c] = -xr[c] / dm;
+                                xr[m] = 1.0 / dm;
+                            }
+                            const double lim = (hv && li > m) ? Tm[tri(i, c0 + m)] : 0.0;
+#pragma unroll
+                            for (int c = 0; c <= m; ++c) {
+                                const double xmc = lane_value(xr[c], m);
+                                if (li > m) xr[c] += lim * xmc;
+                            }
+                        }
+                    }
+                    if (hv) {
+#pragma unroll
+                        for (int c = 0; c < 16; ++c)
+                            if (c <= li) Tm[tri(i, c0 + c)] = xr[c];
+                    }
+                }
+                __syncthreads();
+                double* Ts = Hb;   // [nb - 1][16][16] sums of a block row
+                for (int ib = 1; ib < nb; ++ib) {
+                    // T_j = sum_{k=j}^{ib-1} L_ib,k X_k,j for every block j < ib
+                    for (int jb = wave; jb < ib; jb += MT / 64) {
+                        mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+                        const int ia = 16 * ib + li;
+                        for (int kb = jb; kb < ib; ++kb) {
+#pragma unroll
+                            for (int k0 = 0; k0 < 16; k0 += 4) {
+                                const int kc = 16 * kb + k0 + lk, jc = 16 * jb + li;
+                                const double av = (ia < n && kc < n) ? Tm[tri(ia, kc)] : 0.0;
+                                const double bv = (kc < n && jc <= kc) ? Tm[tri(kc, jc)] : 0.0;
+                                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+                            }
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Ts[(jb * 16 + 4 * r + lk) * 16 + li] = c[r];
+                    }
+                    __syncthreads();
+                    // X_ib,j = -X_ib,ib T_j
+                    for (int jb = wave; jb < ib; jb += MT / 64) {
+                        mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+                        const int ia = 16 * ib + li;
+#pragma unroll
+                        for (int k0 = 0; k0 < 16; k0 += 4) {
+                            const int kc = 16 * ib + k0 + lk;
+                            const double av = (ia < n && kc <= ia) ? -Tm[tri(ia, kc)] : 0.0;
+                            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ts[(jb * 16 + k0 + lk) * 16 + li], c, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int ii = 16 * ib + 4 * r + lk, jj = 16 * jb + li;
+                            if (ii < n) Tm[tri(ii, jj)] = c[r];
+                        }
+                    }
+                    __syncthreads();
+                }
+            } else {
             // ---- L^{-1} in place, one barrier per column: row k of X = L^{-1} is
             //      used unscaled (times 1/L_kk on the fly) and scaled during the
             //      next phase; column k+1 of L is copied aside in phase k (two
@@ -389,6 +473,7 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                 if (tid == 0) Tm[tri(n - 1, n - 1)] = rp;
             }
             __syncthreads();
+            }
             // ---- w = L^{-T} u, then k = dK w
             for (int b = tid; b < n; b += MT) {
                 double s = 0.0;
