@@ -33,7 +33,8 @@
 //   * forms w = K^{-1} Y = L^{-T} u and k = dK w, and from them
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
-//     K^{-1} = L^{-T} L^{-1} computed as they are used, and
+//     K^{-1} = L^{-T} L^{-1} computed as they are used (for designs of 65
+//     to 128 points 16 x 16 tiles of them on the FP64 matrix cores), and
 //     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of columns of
 //     H = dK L^{-T} at a time: for designs of up to 128 points 16 columns on
 //     the FP64 matrix cores, then the same columns of L^{-1} H; larger
@@ -60,6 +61,9 @@ namespace {
 
 constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product (designs above MF points)
 constexpr int MF = 128; // designs of up to MF points take the panel products on the matrix cores
+constexpr int MKI = 64; // ... and above MKI points the K^{-1} entries of the elementwise traces
+                        // (below it the per-entry dot products are short and the padded
+                        // diagonal tiles waste more than the matrix cores save)
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
@@ -513,6 +517,40 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
             }
             // off-diagonal pairs a > b: K^{-1}_ab = sum_{k >= a} Li_ka Li_kb
             const double r2t = 2.0 / theta;
+            if (nm <= MF && n > MKI) {
+                // 16 x 16 tiles (ta, tb), ta >= tb, of K^{-1} = L^{-T} L^{-1} on
+                // the matrix cores (rows k from 16 ta on: Li_ka = 0 for k < a),
+                // then each lane's entries with a > b
+                const int np16 = (n + 15) & ~15, nt = np16 / 16, ntile = nt * (nt + 1) / 2;
+                const int lane = tid & 63, wave = tid >> 6;
+                const int li = lane & 15, lk = lane >> 4;
+                for (int t = wave; t < ntile; t += MT / 64) {
+                    int ta = 0;
+                    while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+                    const int tb = t - ta * (ta + 1) / 2;
+                    const int ai = 16 * ta + li, bj = 16 * tb + li;
+                    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+                    for (int k0 = 16 * ta; k0 < np16; k0 += 4) {
+                        const int k = k0 + lk;
+                        const double av = (k < n && ai <= k) ? Tm[tri(k, ai)] : 0.0;   // A[i][kk] = Li_{k, a_i}
+                        const double bv = (k < n && bj <= k) ? Tm[tri(k, bj)] : 0.0;   // B[kk][j] = Li_{k, b_j}
+                        c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int a = 16 * ta + 4 * r + lk, b = bj;
+                        if (a < n && b < a) {
+                            const double ki = c[r];
+                            const double kd = Cd[sl(a, b)];
+                            const double d2 = sqdist_rows(xs, a, b, p);
+                            const double kdd = kd * (d2 / th2 - r2t);
+                            acc[3] += 2.0 * (w[a] * w[b]) * kdd;
+                            acc[4] += 2.0 * ki * kd;
+                            acc[5] += 2.0 * ki * kdd;
+                        }
+                    }
+                }
+            } else {
             const int nsl = n * (n - 1) / 2;
             for (int e = tid; e < nsl; e += MT) {
                 const int a = row_of(e) + 1, b = e - half_prod(a, a - 1);
@@ -530,6 +568,7 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                 acc[3] += 2.0 * (w[a] * w[b]) * kdd;
                 acc[4] += 2.0 * ki * kd;
                 acc[5] += 2.0 * ki * kdd;
+            }
             }
             // ---- tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2
             if (nm <= MF) {
