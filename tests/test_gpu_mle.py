@@ -115,6 +115,27 @@ def test_mle_uneven_sizes_and_starts(c2, lagp):
     _check_mle(w, sel, d0, th, it, st, tmin, tmax, n_per=n_per)
 
 
+def test_mle_designs_above_128_points(lagp):
+    """A batch whose largest design has more than 128 points (130 at p = 2,
+    about the most the LDS holds) runs the per-column factorisation, the
+    Gauss-Jordan inverse and the vector-unit panels for all of its
+    locations; sizes from 2 to 130, one of them ending on the upper bound."""
+    import types
+    r = np.random.default_rng(23)
+    X = r.uniform(0, 1, (3000, 2))
+    y = np.sin(5 * X[:, 0]) * np.cos(3 * X[:, 1]) + 0.05 * r.standard_normal(3000)
+    w = types.SimpleNamespace(X=X, y=y, g=1e-3)
+    D = lagp.Design(X, y)
+    XX = r.uniform(0.1, 0.9, (12, 2))
+    n_per = np.array([130, 129, 2, 17, 64, 65, 100, 128, 130, 129, 77, 3], np.int32)
+    sel = np.full((len(XX), 130), -7, np.int32)
+    for t in range(len(XX)):
+        sel[t, :n_per[t]] = oracle.knn(X, XX[t], int(n_per[t]))[0]
+    tmin, tmax = workloads.mle_range(X)
+    th, it, st = _mle_gpu(D, sel, 0.1, w.g, tmin, tmax, n_per=n_per)
+    _check_mle(w, sel, 0.1, th, it, st, tmin, tmax, n_per=n_per)
+
+
 def test_mle_boundary_and_failures(lagp):
     """Two-point designs whose likelihood is monotone end on a bound; a design
     with an index outside the data or without a nugget on duplicated points
