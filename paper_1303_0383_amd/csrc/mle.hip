@@ -239,17 +239,23 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                                 if (!(pm > 0.0)) {
                                     f = 1;   // uniform: every lane read the same pivot
                                 } else {
-                                    const double dp = sqrt(pm);
-                                    const double um = lane_value(u0, q) / dp;
-                                    if (lane == q) u0 = um;
-                                    if (lane == 0) piv[c0 + q] = dp;
-                                    if (lane > q) r0[q] = r0[q] / dp;   // rows below the pivot
+                                    // the update uses the column unscaled (times the
+                                    // reciprocal of the unrooted pivot), so the root and
+                                    // the scaling stay off the chain to the next pivot
+                                    const double rpm = 1.0 / pm;
+                                    const double t = r0[q] * rpm;
+                                    const double uq = lane_value(u0, q);
 #pragma unroll
                                     for (int qq = q + 1; qq < 16; ++qq) {
-                                        const double lkm = lane_value(r0[q], qq);   // L_km, row k = c0 + qq
-                                        if (lane >= qq) r0[qq] -= r0[q] * lkm;
+                                        const double akm = lane_value(r0[q], qq);   // unscaled A_km, row k = c0 + qq
+                                        if (lane >= qq) r0[qq] -= t * akm;
                                     }
-                                    if (lane > q) u0 -= r0[q] * um;
+                                    if (lane > q) u0 -= t * uq;
+                                    // L_kq = A_kq / sqrt(pm) = t sqrt(pm); u_q / sqrt(pm) = u_q sqrt(pm) / pm
+                                    const double dp = sqrt(pm);
+                                    if (lane == 0) piv[c0 + q] = dp;
+                                    if (lane > q) r0[q] = t * dp;   // rows below the pivot
+                                    if (lane == q) u0 = u0 * (dp * rpm);
                                 }
                             }
                         }
@@ -375,16 +381,16 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                     double xr[16];
 #pragma unroll
                     for (int c = 0; c < 16; ++c) xr[c] = 0.0;   // sums of L_im X_mc over m < i
+                    const double rd = hv ? 1.0 / piv[i] : 0.0;   // 1 / L_ii, formed by all rows at once
 #pragma unroll
                     for (int m = 0; m < 16; ++m) {
                         if (c0 + m < n) {
                             // row m finishes: X_mc = -sum / L_mm (c < m), X_mm = 1 / L_mm
                             if (lane == m) {
-                                const double dm = piv[c0 + m];
 #pragma unroll
                                 for (int c = 0; c < 16; ++c)
-                                    if (c < m) xr[c] = -xr[c] / dm;
-                                xr[m] = 1.0 / dm;
+                                    if (c < m) xr[c] = -xr[c] * rd;
+                                xr[m] = rd;
                             }
                             const double lim = (hv && li > m) ? Tm[tri(i, c0 + m)] : 0.0;
 #pragma unroll
