@@ -245,10 +245,13 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                                     const double rpm = 1.0 / pm;
                                     const double t = r0[q] * rpm;
                                     const double uq = lane_value(u0, q);
+                                    // every lane updates (no select): lanes above row
+                                    // c0 + qq change only entries above the diagonal,
+                                    // which are never read as pivots or stored
 #pragma unroll
                                     for (int qq = q + 1; qq < 16; ++qq) {
                                         const double akm = lane_value(r0[q], qq);   // unscaled A_km, row k = c0 + qq
-                                        if (lane >= qq) r0[qq] -= t * akm;
+                                        r0[qq] -= t * akm;
                                     }
                                     if (lane > q) u0 -= t * uq;
                                     // L_kq = A_kq / sqrt(pm) = t sqrt(pm); u_q / sqrt(pm) = u_q sqrt(pm) / pm
