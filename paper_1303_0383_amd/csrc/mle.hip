@@ -30,7 +30,8 @@
 //     larger ones by Gauss-Jordan elimination, one barrier per column (each
 //     row scaled during the next phase, the next column of L copied aside
 //     first);
-//   * forms w = K^{-1} Y = L^{-T} u and k = dK w, and from them
+//   * forms w = K^{-1} Y = L^{-T} u and k = dK w (each dot product split
+//     over a few lanes of one wave), and from them
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
 //     K^{-1} = L^{-T} L^{-1} computed as they are used (for designs of 65
@@ -487,42 +488,49 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
             }
             __syncthreads();
             }
-            // ---- w = L^{-T} u, then k = dK w
-            for (int b = tid; b < n; b += MT) {
+            // ---- w = L^{-T} u, then k = dK w, then z = L^{-1} k: each dot
+            //      product taken by P lanes of one wave (P a power of two, as
+            //      many as the workgroup's threads allow for the design, at most
+            //      8), lane part pp summing the terms pp, pp + P, ..., the parts
+            //      added across the P lanes (the same sum in every lane: the
+            //      butterfly adds the same pairs in each)
+            int lp = 0;
+            while (lp < 3 && (2 << lp) * n <= MT) ++lp;
+            const int P = 1 << lp, pp = tid & (P - 1), rstep = MT >> lp;
+            for (int b = tid >> lp; b < n; b += rstep) {
                 double s = 0.0;
-                int o = tri(b, b);                 // (a, b), a = b, b + 1, ...: steps of a + 1
-#pragma unroll 4
-                for (int a = b; a < n; ++a) {
+                int o = tri(b + pp, b);            // (a, b), a = b + pp, b + pp + P, ...
+                for (int a = b + pp; a < n; a += P) {
                     s += Tm[o] * u[a];
-                    o += a + 1;
+                    o += a * P + ((P * (P + 1)) >> 1);
                 }
-                w[b] = s;
+                for (int m = 1; m < P; m <<= 1) s += __shfl_xor(s, m);
+                if (pp == 0) w[b] = s;
             }
             __syncthreads();
-            for (int a = tid; a < n; a += MT) {
+            for (int a = tid >> lp; a < n; a += rstep) {
                 double s = 0.0;
                 const double* ca = Cd + sl(a, 0);
-#pragma unroll 4
-                for (int b = 0; b < a; ++b) s += ca[b] * w[b];
-                int o = sl(a + 1, a);              // (b, a), b = a + 1, ...: steps of b
-#pragma unroll 4
-                for (int b = a + 1; b < n; ++b) {
-                    s += Cd[o] * w[b];
-                    o += b;
-                }
-                kw[a] = s;
+                int b = pp;
+                for (; b < a; b += P) s += ca[b] * w[b];
+                if (b == a) b += P;                // dK_aa = 0
+                for (; b < n; b += P) s += Cd[sl(b, a)] * w[b];
+                for (int m = 1; m < P; m <<= 1) s += __shfl_xor(s, m);
+                if (pp == 0) kw[a] = s;
             }
             __syncthreads();
             // sums: 0 psi, 1 q, 2 sq, 3 r, 4 t1, 5 t2, 6 t3
             double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int a = tid; a < n; a += MT) {
-                acc[0] += u[a] * u[a];
-                acc[1] += w[a] * kw[a];
+            for (int a = tid >> lp; a < n; a += rstep) {
                 double z = 0.0;
                 const double* la = Tm + tri(a, 0);
-#pragma unroll 4
-                for (int b = 0; b <= a; ++b) z += la[b] * kw[b];
-                acc[2] += z * z;
+                for (int b = pp; b <= a; b += P) z += la[b] * kw[b];
+                for (int m = 1; m < P; m <<= 1) z += __shfl_xor(z, m);
+                if (pp == 0) {
+                    acc[0] += u[a] * u[a];
+                    acc[1] += w[a] * kw[a];
+                    acc[2] += z * z;
+                }
             }
             // off-diagonal pairs a > b: K^{-1}_ab = sum_{k >= a} Li_ka Li_kb
             const double r2t = 2.0 / theta;
