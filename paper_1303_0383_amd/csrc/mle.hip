@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                     const int tb = t - ta * (ta + 1) / 2;
                     const int ai = 16 * ta + li, bj = 16 * tb + li;
                     mf_d4 c = {0.0, 0.0, 0.0, 0.0};
-                    for (int k0 = 16 * ta; k0 < np16; k0 += 4) {
+                    for (int k0 = 16 * ta; k0 < n; k0 += 4) {   // rows k >= n add zeros
                         const int k = k0 + lk;
                         const double av = (k < n && ai <= k) ? Tm[tri(k, ai)] : 0.0;   // A[i][kk] = Li_{k, a_i}
                         const double bv = (k < n && bj <= k) ? Tm[tri(k, bj)] : 0.0;   // B[kk][j] = Li_{k, b_j}
@@ -605,7 +605,9 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                     for (int tw = wave; tw < nt; tw += MT / 64) {
                         const int a = 16 * tw + li;   // row of dK
                         mf_d4 c = {0.0, 0.0, 0.0, 0.0};
-                        for (int k0 = 0; k0 < np16; k0 += 4) {
+                        // b <= j < 16 q + 16 and b < n: later steps add zeros
+                        const int kend = n < 16 * q + 16 ? n : 16 * q + 16;
+                        for (int k0 = 0; k0 < kend; k0 += 4) {
                             const int b = k0 + lk;
                             double av = 0.0, bv = 0.0;
                             if (a < n && b < n && a != b) av = a > b ? Cd[sl(a, b)] : Cd[sl(b, a)];
@@ -619,7 +621,9 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                     for (int tw = wave; tw < nt; tw += MT / 64) {
                         const int i = 16 * tw + li;   // row of L^{-1} and M
                         mf_d4 c = {0.0, 0.0, 0.0, 0.0};
-                        for (int k0 = 0; k0 < np16; k0 += 4) {
+                        // a <= i < 16 tw + 16 and a < n: later steps add zeros
+                        const int kend = n < 16 * tw + 16 ? n : 16 * tw + 16;
+                        for (int k0 = 0; k0 < kend; k0 += 4) {
                             const int a = k0 + lk;
                             const double av = (i < n && a <= i) ? Tm[tri(i, a)] : 0.0;
                             c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Hb[a * 16 + li], c, 0, 0, 0);
