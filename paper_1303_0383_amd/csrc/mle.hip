@@ -430,15 +430,18 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                         for (int r = 0; r < 4; ++r) Ts[(jb * 16 + 4 * r + lk) * 16 + li] = c[r];
                     }
                     __syncthreads();
-                    // X_ib,j = -X_ib,ib T_j
+                    // X_ib,j = -X_ib,ib T_j (columns of X_ib,ib past n - 16 ib are zero)
+                    const int kend = n - 16 * ib < 16 ? n - 16 * ib : 16;
                     for (int jb = wave; jb < ib; jb += MT / 64) {
                         mf_d4 c = {0.0, 0.0, 0.0, 0.0};
                         const int ia = 16 * ib + li;
 #pragma unroll
                         for (int k0 = 0; k0 < 16; k0 += 4) {
-                            const int kc = 16 * ib + k0 + lk;
-                            const double av = (ia < n && kc <= ia) ? -Tm[tri(ia, kc)] : 0.0;
-                            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ts[(jb * 16 + k0 + lk) * 16 + li], c, 0, 0, 0);
+                            if (k0 < kend) {   // uniform
+                                const int kc = 16 * ib + k0 + lk;
+                                const double av = (ia < n && kc <= ia) ? -Tm[tri(ia, kc)] : 0.0;
+                                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ts[(jb * 16 + k0 + lk) * 16 + li], c, 0, 0, 0);
+                            }
                         }
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -593,8 +596,9 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                 // the design padded with zero rows and columns to np16 = 16
                 // ceil(n/16): a 16-column panel of H = dK L^{-T} (one 16 x 16
                 // tile per wave), staged in LDS, then the same columns of
-                // M = L^{-1} H, whose squared entries (all of them: M is
-                // symmetric) sum to the trace.  Operand layout of the
+                // M = L^{-1} H, whose squared entries sum to the trace (M is
+                // symmetric: the tiles on and below the diagonal, those below
+                // counted twice).  Operand layout of the
                 // instruction: A[i][k] and B[k][j] come from lane i + 16 k and
                 // j + 16 k, and lane l's result r is D[4 r + l / 16][l % 16].
                 const int np16 = (n + 15) & ~15, nt = np16 / 16;
@@ -619,6 +623,7 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                     }
                     __syncthreads();
                     for (int tw = wave; tw < nt; tw += MT / 64) {
+                        if (tw < q) continue;   // M is symmetric: tiles above the diagonal mirror those below
                         const int i = 16 * tw + li;   // row of L^{-1} and M
                         mf_d4 c = {0.0, 0.0, 0.0, 0.0};
                         // a <= i < 16 tw + 16 and a < n: later steps add zeros
@@ -628,8 +633,9 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                             const double av = (i < n && a <= i) ? Tm[tri(i, a)] : 0.0;
                             c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Hb[a * 16 + li], c, 0, 0, 0);
                         }
+                        const double wt = tw == q ? 1.0 : 2.0;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[6] += c[r] * c[r];
+                        for (int r = 0; r < 4; ++r) acc[6] += wt * (c[r] * c[r]);
                     }
                     __syncthreads();
                 }
