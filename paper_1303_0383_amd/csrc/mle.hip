@@ -34,7 +34,7 @@
 //     over a few lanes of one wave), and from them
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
-//     K^{-1} = L^{-T} L^{-1} computed as they are used (for designs of 65
+//     K^{-1} = L^{-T} L^{-1} computed as they are used (for designs of up
 //     to 128 points 16 x 16 tiles of them on the FP64 matrix cores), and
 //     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of columns of
 //     H = dK L^{-T} at a time: for designs of up to 128 points 16 columns on
@@ -62,9 +62,6 @@ namespace {
 
 constexpr int PW = 8;   // panel width of the tr((K^{-1} dK)^2) product (designs above MF points)
 constexpr int MF = 128; // designs of up to MF points take the panel products on the matrix cores
-constexpr int MKI = 64; // ... and above MKI points the K^{-1} entries of the elementwise traces
-                        // (below it the per-entry dot products are short and the padded
-                        // diagonal tiles waste more than the matrix cores save)
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
@@ -537,7 +534,7 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
             }
             // off-diagonal pairs a > b: K^{-1}_ab = sum_{k >= a} Li_ka Li_kb
             const double r2t = 2.0 / theta;
-            if (nm <= MF && n > MKI) {
+            if (nm <= MF) {
                 // 16 x 16 tiles (ta, tb), ta >= tb, of K^{-1} = L^{-T} L^{-1} on
                 // the matrix cores (rows k from 16 ta on: Li_ka = 0 for k < a),
                 // then each lane's entries with a > b
