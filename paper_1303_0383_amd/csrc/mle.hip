@@ -38,9 +38,10 @@
 //     to 128 points 16 x 16 tiles of them on the FP64 matrix cores), and
 //     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of columns of
 //     H = dK L^{-T} at a time: for designs of up to 128 points 16 columns on
-//     the FP64 matrix cores, then the same columns of L^{-1} H; larger
-//     designs PW columns on the vector unit (one panel formed while the
-//     previous one is used);
+//     the FP64 matrix cores, then the same columns of L^{-1} H (its tiles
+//     on and below the diagonal: the product is symmetric), every product
+//     stopping at its last nonzero term; larger designs PW columns on the
+//     vector unit (one panel formed while the previous one is used);
 //   * takes the safeguarded Newton step on l'(theta) = 0.
 // The step rule: where l'' < 0 the step is -l'/l''; elsewhere it is theta in
 // the direction of l'; a step leaving (tmin, tmax) goes half way to the
