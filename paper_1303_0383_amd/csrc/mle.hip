@@ -35,7 +35,9 @@
 //     psi = u'u, q = w'k, sq = ||L^{-1} k||^2 and r = w' d2K w;
 //   * forms tr(K^{-1} dK) and tr(K^{-1} d2K) with the entries of
 //     K^{-1} = L^{-T} L^{-1} computed as they are used (for designs of up
-//     to 128 points 16 x 16 tiles of them on the FP64 matrix cores), and
+//     to 128 points 16 x 16 tiles of them on the FP64 matrix cores, the
+//     pairs' squared distances for d2K from tiles of x_a . x_b and the
+//     points' norms), and
 //     tr((K^{-1} dK)^2) = ||L^{-1} dK L^{-T}||_F^2 a panel of columns of
 //     H = dK L^{-T} at a time: for designs of up to 128 points 16 columns on
 //     the FP64 matrix cores, then the same columns of L^{-1} H (its tiles
@@ -173,6 +175,17 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
     if (!bad) {
         for (int e = tid; e < n * p; e += MT) xs[e] = A.Xaos[(int64_t)D[e / p] * p + e % p];
         for (int a = tid; a < n; a += MT) yv[a] = A.y[D[a]];
+        if (nm <= MF) {
+            // squared norms of the design points (in the column buffers, which
+            // only the Gauss-Jordan form of larger designs uses), for the
+            // distances of the trace sums: |x_a - x_b|^2 = |x_a|^2 + |x_b|^2 - 2 x_a.x_b
+            __syncthreads();
+            for (int a = tid; a < n; a += MT) {
+                double s = 0.0;
+                for (int c = 0; c < p; ++c) s += xs[a * p + c] * xs[a * p + c];
+                col[a] = s;
+            }
+        }
         const double th0 = A.theta0_per ? A.theta0_per[t] : A.theta0;
         theta = (th0 > A.tmin && th0 < A.tmax) ? th0 : sqrt(A.tmin * A.tmax);
         const int ntri = n * (n + 1) / 2;
@@ -554,13 +567,22 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                         const double bv = (k < n && bj <= k) ? Tm[tri(k, bj)] : 0.0;   // B[kk][j] = Li_{k, b_j}
                         c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
                     }
+                    // the same tile of x_a . x_b, p coordinates at a time
+                    mf_d4 g = {0.0, 0.0, 0.0, 0.0};
+                    for (int k0 = 0; k0 < p; k0 += 4) {
+                        const int k = k0 + lk;
+                        const double xa = (ai < n && k < p) ? xs[ai * p + k] : 0.0;
+                        const double xb = (bj < n && k < p) ? xs[bj * p + k] : 0.0;
+                        g = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, xb, g, 0, 0, 0);
+                    }
+                    const double nb = bj < n ? col[bj] : 0.0;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int a = 16 * ta + 4 * r + lk, b = bj;
                         if (a < n && b < a) {
                             const double ki = c[r];
                             const double kd = Cd[sl(a, b)];
-                            const double d2 = sqdist_rows(xs, a, b, p);
+                            const double d2 = (col[a] + nb) - 2.0 * g[r];
                             const double kdd = kd * (d2 / th2 - r2t);
                             acc[3] += 2.0 * (w[a] * w[b]) * kdd;
                             acc[4] += 2.0 * ki * kd;
