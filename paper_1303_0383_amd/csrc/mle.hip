@@ -408,10 +408,11 @@ __global__ void __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(4))) ml
                                 xr[m] = rd;
                             }
                             const double lim = (hv && li > m) ? Tm[tri(i, c0 + m)] : 0.0;
+                            // lim is zero on the rows at and above m (no select needed)
 #pragma unroll
                             for (int c = 0; c <= m; ++c) {
                                 const double xmc = lane_value(xr[c], m);
-                                if (li > m) xr[c] += lim * xmc;
+                                xr[c] += lim * xmc;
                             }
                         }
                     }
